@@ -1,0 +1,133 @@
+/*
+ * szx.h -- C ABI of the MI355X (gfx950) implementation of the SZx block-wise
+ * error-bounded lossy compressor (Yu et al., "SZx: an Ultra-fast Error-bounded
+ * Lossy Compressor for Scientific Datasets", arXiv 2201.13020).
+ *
+ * The method (Sec. IV, Alg. 1): the flattened field is cut into fixed 1-D
+ * blocks of b values. A block whose values all lie within e of mu, the mean of
+ * the block's min and max, is stored as mu alone ("constant" block). Every
+ * other block stores mu, the count K of leading IEEE-754 bits kept of each
+ * normalised value v = x - mu (eq. (4)), right-shifted so the kept bits fill
+ * whole bytes (eq. (5), Sec. V-A), and, per value, a 2-bit code of the leading
+ * bytes it shares with its predecessor plus the remaining ("mid") bytes.
+ * Decompression inverts this (Sec. V-B). Every reconstructed value x' obeys
+ * |x - x'| <= e (eq. (1)).
+ *
+ * All device pointers are plain HIP device addresses; every buffer is owned
+ * by the caller. Calls that take a stream are asynchronous on that stream:
+ * they validate arguments on the host, enqueue kernels, and return. They never
+ * allocate device memory and never synchronise, so they may be captured in a
+ * HIP graph. Results that only the device knows (the compressed size, decode
+ * errors) are written to device memory.
+ *
+ * Stream layout (format version 1; little-endian):
+ *   96-byte header: magic "SZXM", version, dtype, eb_mode, ndims, b, dims[4],
+ *   N, eb as given, bit pattern of e, nblk, n_nc (non-constant blocks),
+ *   mid_total; then five sections, each starting at a multiple of 16 bytes:
+ *   state bits (1 = non-constant, LSB-first), mu[nblk] (T), K[n_nc] (u8,
+ *   0xFF = raw block), codes[n_nc * b/4] (4 per byte, first value in the top
+ *   two bits), mid bytes[mid_total] (values in order, kept bytes most
+ *   significant first; raw blocks hold the values' little-endian bytes).
+ */
+#ifndef SZX_H
+#define SZX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Element type of the field. */
+typedef enum { SZ_F32 = 0, SZ_F64 = 1 } sz_dtype;
+
+/* SZ_ABS: e = eb. SZ_REL: e = eb * (max - min) over the field's finite values,
+   the value-range based relative bound of Sec. III (footnote) and Sec. VI.
+   In both modes e is then rounded down to the element type. */
+typedef enum { SZ_ABS = 0, SZ_REL = 1 } sz_eb_mode;
+
+typedef enum {
+  SZ_OK = 0,
+  SZ_EINVAL = 1,       /* bad argument (null pointer, bad parameter, misaligned buffer) */
+  SZ_ENOSPC = 2,       /* output or workspace capacity too small */
+  SZ_ECORRUPT = 3,     /* stream failed validation (sz_inspect, or *d_status) */
+  SZ_EDEVICE = 4,      /* a HIP call failed; see sz_last_error() */
+  SZ_ENOMEM = 5,       /* reserved */
+  SZ_EUNSUPPORTED = 6  /* parameters beyond this build's limits */
+} sz_status;
+
+/* Parameters of one field. Dims are metadata: blocks run over the row-major
+   flattening (Sec. IV: "many small 1D blocks"), N = dims[0]*...*dims[ndims-1]. */
+typedef struct {
+  uint32_t dtype;      /* sz_dtype */
+  uint32_t ndims;      /* 1..4 */
+  uint64_t dims[4];    /* unused entries must be 0 */
+  uint32_t eb_mode;    /* sz_eb_mode */
+  uint32_t block_size; /* b: a power of two in [8, 1024]; the paper's choice is 128 (Sec. V-A) */
+  double eb;           /* >= 0 and finite */
+} sz_params;
+
+/* Upper bound of the compressed size in bytes for these parameters (every
+   block stored raw, plus header and section padding). 0 if the parameters are
+   invalid. Host only, pure. */
+uint64_t sz_compress_bound(const sz_params* p);
+
+/* Device workspace in bytes that sz_compress and sz_decompress need for these
+   parameters (per-block extrema, the list of non-constant blocks, tile status
+   words of the single-pass scans, counters). 0 if the parameters are invalid.
+   Host only, pure. The workspace holds no state between calls. */
+uint64_t sz_workspace_size(const sz_params* p);
+
+/* Compress N values of p->dtype at d_in (device, 16-byte aligned) into d_out
+   (device, 16-byte aligned, out_cap bytes, out_cap >= sz_compress_bound(p)).
+   Writes the stream size (bytes) to *d_out_size (device u64); 0 there means a
+   device-side failure. d_ws: device workspace of ws_bytes >= sz_workspace_size(p),
+   16-byte aligned. Asynchronous on `stream`.
+   Errors (returned, nothing enqueued): SZ_EINVAL, SZ_ENOSPC, SZ_EUNSUPPORTED,
+   SZ_EDEVICE (launch failure). Implements Alg. 1 of Sec. IV with the GPU
+   organisation of Sec. V-B (per-block classification, then encoding of the
+   non-constant blocks with a prefix scan for their output offsets). */
+sz_status sz_compress(const sz_params* p, const void* d_in, void* d_out,
+                      uint64_t out_cap, uint64_t* d_out_size, void* d_ws,
+                      uint64_t ws_bytes, hipStream_t stream);
+
+/* Decompress the stream at d_in (device, 16-byte aligned, in_bytes bytes) into
+   d_out (device, 16-byte aligned, out_cap >= N * sizeof(T) bytes). `expected`
+   gives the field's dtype, dims and block size (from sz_inspect on a host copy
+   of the header, or from the caller's own metadata); the kernels check the
+   device header against it. *d_status (device u32) receives SZ_OK or
+   SZ_ECORRUPT; on SZ_ECORRUPT the output is unspecified but no access leaves
+   the given buffers. d_ws as for sz_compress, sized with `expected`.
+   Asynchronous on `stream`. Sec. V-B: leading bytes are resolved by a parallel
+   scan over the 2-bit codes, mid bytes are located by a prefix scan. */
+sz_status sz_decompress(const void* d_in, uint64_t in_bytes,
+                        const sz_params* expected, void* d_out, uint64_t out_cap,
+                        uint32_t* d_status, void* d_ws, uint64_t ws_bytes,
+                        hipStream_t stream);
+
+/* Parse a host copy of a stream header (at least 96 bytes). Fills *out and
+   *total_bytes (the full stream size). Returns SZ_ECORRUPT for a bad header,
+   SZ_EINVAL for null pointers. Host only. */
+sz_status sz_inspect(const void* h_hdr, uint64_t bytes, sz_params* out,
+                     uint64_t* total_bytes);
+
+/* Message of the last error returned on the calling thread ("" if none). */
+const char* sz_last_error(void);
+
+/* Optional per-kernel timing for measurement. When enabled, every kernel the
+   library enqueues is bracketed by HIP events on its stream; sz_timing_read
+   waits for them and returns, per kernel name, the number of launches and
+   their summed duration in milliseconds since the last read (then resets).
+   `names` receives pointers to static strings. Returns the number of entries
+   written (at most cap). Not for use under graph capture. */
+void sz_timing_enable(int on);
+uint32_t sz_timing_read(const char** names, double* total_ms, uint32_t* launches,
+                        uint32_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,328 @@
+// szx_device.hpp -- device-side building blocks of the SZx kernels for gfx950.
+//
+// Element traits, IEEE-754 totalOrder keys, the exact "a - c <= e" decision,
+// the bit budget of eq. (4) with the byte shift of eq. (5), wave/group scans,
+// the workgroup-wide scan, and the decoupled look-back that chains tiles of a
+// single-pass device-wide prefix sum (Sec. V-B: the output offset of each
+// block is the prefix sum of the bytes of the blocks before it).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace szx {
+
+constexpr int kWave = 64;
+constexpr int kWG = 256;
+constexpr int kWavesPerWG = kWG / kWave;
+constexpr uint32_t kHeaderBytes = 96;
+constexpr uint32_t kMagic = 0x4D585A53u;  // "SZXM" little-endian
+constexpr uint8_t kVersion = 1;
+constexpr uint8_t kRawK = 0xFF;
+
+template <typename T>
+struct Traits;
+
+template <>
+struct Traits<float> {
+  using U = uint32_t;
+  static constexpr int W = 32;     // bits per value
+  static constexpr int E = 8;      // exponent bits
+  static constexpr int BIAS = 127;
+  static constexpr int BYTES = 4;
+  static constexpr int KMIN = 1 + E;
+};
+
+template <>
+struct Traits<double> {
+  using U = uint64_t;
+  static constexpr int W = 64;
+  static constexpr int E = 11;
+  static constexpr int BIAS = 1023;
+  static constexpr int BYTES = 8;
+  static constexpr int KMIN = 1 + E;
+};
+
+// Launch geometry that depends only on the block size b: each lane owns EPL
+// consecutive values, LPB lanes share one block, a 256-thread workgroup tile
+// holds TB whole blocks. It changes no output byte.
+template <typename T, int B>
+struct Geo {
+  static constexpr int EPL = B >= 512 ? B / 64 : 8;
+  static constexpr int LPB = B / EPL;  // 1..64, divides 64
+  static constexpr int TB = kWG / LPB;
+  static constexpr int TILE = TB * B;  // values per tile
+  static_assert(LPB >= 1 && LPB <= 64 && (64 % LPB) == 0, "group must fit a wave");
+};
+
+__device__ __forceinline__ uint32_t bits_of(float v) { return __float_as_uint(v); }
+__device__ __forceinline__ uint64_t bits_of(double v) { return (uint64_t)__double_as_longlong(v); }
+__device__ __forceinline__ float float_from(uint32_t u) { return __uint_as_float(u); }
+__device__ __forceinline__ double double_from(uint64_t u) { return __longlong_as_double((long long)u); }
+
+template <typename T>
+__device__ __forceinline__ T from_bits(typename Traits<T>::U u);
+template <>
+__device__ __forceinline__ float from_bits<float>(uint32_t u) { return float_from(u); }
+template <>
+__device__ __forceinline__ double from_bits<double>(uint64_t u) { return double_from(u); }
+
+// Unsigned key whose order is IEEE-754 totalOrder (-0 < +0): flip all bits of
+// negatives, set the sign bit of non-negatives.
+template <typename U>
+__device__ __forceinline__ U order_key(U u) {
+  constexpr U sign = (U)1 << (sizeof(U) * 8 - 1);
+  return (u & sign) ? (U)~u : (U)(u | sign);
+}
+template <typename U>
+__device__ __forceinline__ U key_to_bits(U k) {
+  constexpr U sign = (U)1 << (sizeof(U) * 8 - 1);
+  return (k & sign) ? (U)(k & ~sign) : (U)~k;
+}
+
+// Keys of -max finite and +max finite: a block is all-finite iff its key range
+// lies inside [kLo, kHi].
+template <typename T>
+struct FiniteKeys {
+  using U = typename Traits<T>::U;
+  static constexpr U EXPMASK = (((U)1 << Traits<T>::E) - 1) << (Traits<T>::W - 1 - Traits<T>::E);
+  static constexpr U SIGN = (U)1 << (Traits<T>::W - 1);
+  static constexpr U MAXF = EXPMASK - 1;          // largest finite magnitude pattern
+  static constexpr U HI = MAXF | SIGN;            // key of +max
+  static constexpr U LO = (U)~(MAXF | SIGN);      // key of -max
+};
+
+template <typename T>
+__device__ __forceinline__ bool is_finite_bits(typename Traits<T>::U u) {
+  return (u & FiniteKeys<T>::EXPMASK) != FiniteKeys<T>::EXPMASK;
+}
+
+// Exact decision of (a - c) <= e for finite a, c, e whose difference does not
+// overflow. s = fl(a - c) lies on the same side of e as the exact difference
+// whenever s != e (rounding is monotone); when s == e the rounding error,
+// recovered exactly by Knuth's TwoSum, decides.
+template <typename T>
+__device__ __forceinline__ bool exact_le(T a, T c, T e) {
+  const T nb = -c;
+  const T s = a + nb;
+  if (s < e) return true;
+  if (s > e) return false;
+  const T bv = s - a;
+  const T av = s - bv;
+  const T t = (a - av) + (nb - bv);
+  return t <= (T)0;
+}
+
+// p(y) of eq. (4): unbiased exponent of |y|, with zero and subnormals at the
+// smallest normal exponent.
+template <typename T>
+__device__ __forceinline__ int exp_of(T y) {
+  using U = typename Traits<T>::U;
+  const U u = bits_of(y);
+  int f = (int)((u >> (Traits<T>::W - 1 - Traits<T>::E)) & ((1u << Traits<T>::E) - 1));
+  f = f < 1 ? 1 : f;
+  return f - Traits<T>::BIAS;
+}
+
+// Largest T value <= ed, for ed >= 0 (possibly +inf).
+template <typename T>
+__device__ __forceinline__ T round_down_to(double ed);
+template <>
+__device__ __forceinline__ float round_down_to<float>(double ed) {
+  if (!(ed > 0.0)) return 0.0f;
+  if (__builtin_isinf(ed)) return 3.40282346638528859812e+38f;
+  float f = __double2float_rn(ed);
+  if (__builtin_isinf(f)) return 3.40282346638528859812e+38f;
+  while ((double)f > ed) f = __uint_as_float(__float_as_uint(f) - 1u);
+  return f;
+}
+template <>
+__device__ __forceinline__ double round_down_to<double>(double ed) {
+  if (!(ed > 0.0)) return 0.0;
+  if (__builtin_isinf(ed)) return 1.79769313486231570815e+308;
+  return ed;
+}
+
+// Bound e from the parameters and, for REL, the global finite range (keys;
+// lo > hi means no finite value was seen).
+template <typename T>
+__device__ __forceinline__ T bound_from(int rel, double eb, uint64_t klo, uint64_t khi) {
+  using U = typename Traits<T>::U;
+  double ed;
+  if (!rel) {
+    ed = eb;
+  } else if (klo > khi || eb == 0.0) {
+    ed = 0.0;
+  } else {
+    const T gmin = from_bits<T>(key_to_bits<U>((U)klo));
+    const T gmax = from_bits<T>(key_to_bits<U>((U)khi));
+    const double range = (double)gmax - (double)gmin;
+    ed = eb * range;
+  }
+  return round_down_to<T>(ed);
+}
+
+// Kept leading bits K = min(W, 1 + E + m) (eq. (4) read as a count of kept
+// bits: sign, exponent and m mantissa bits), its right shift s (eq. (5)) and
+// the number of whole bytes nb = (K + s) / 8.
+__device__ __forceinline__ int shift_of(int K) { return (8 - (K & 7)) & 7; }
+__device__ __forceinline__ int bytes_of(int K) { return (K + shift_of(K)) >> 3; }
+
+template <typename T>
+__device__ __forceinline__ int kept_bits(int m) {
+  const int k = 1 + Traits<T>::E + m;
+  return k > Traits<T>::W ? Traits<T>::W : k;
+}
+
+// Mid-range and constant test of one block from its totalOrder extrema.
+// Returns true for a constant block. m0 receives the mantissa budget of eq. (4)
+// for a non-constant one.
+template <typename T>
+__device__ __forceinline__ bool classify_block(T mn, T mx, T e, T& mu, int& m0) {
+  mu = (T)0.5 * mn + (T)0.5 * mx;
+  if (exact_le<T>(mx, mu, e) && exact_le<T>(mu, mn, e)) {
+    m0 = 0;
+    return true;
+  }
+  T r1 = mx - mu;
+  T r2 = mn - mu;
+  r1 = r1 < (T)0 ? -r1 : r1;
+  r2 = r2 < (T)0 ? -r2 : r2;
+  const T r = r1 > r2 ? r1 : r2;
+  const int m = exp_of<T>(r) - exp_of<T>(e);
+  m0 = m < 0 ? 0 : m;
+  return false;
+}
+
+// Mask of the top nb bytes of a word.
+template <typename U>
+__device__ __forceinline__ U top_bytes_mask(int nb) {
+  constexpr int W = sizeof(U) * 8;
+  return nb >= W / 8 ? (U)~(U)0 : (nb <= 0 ? (U)0 : (U) ~(((U)1 << (W - 8 * nb)) - 1));
+}
+
+// Count of identical leading bytes of a and b (all bytes when equal).
+__device__ __forceinline__ int same_lead_bytes(uint32_t a, uint32_t b) {
+  const uint32_t z = a ^ b;
+  return z == 0 ? 4 : (__clz(z) >> 3);
+}
+__device__ __forceinline__ int same_lead_bytes(uint64_t a, uint64_t b) {
+  const uint64_t z = a ^ b;
+  return z == 0 ? 8 : (__clzll(z) >> 3);
+}
+
+__device__ __forceinline__ uint32_t byte_swap(uint32_t v) { return __builtin_bswap32(v); }
+__device__ __forceinline__ uint64_t byte_swap(uint64_t v) { return __builtin_bswap64(v); }
+
+// ---------------------------------------------------------------- scans ----
+
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+// Inclusive sum over groups of G consecutive lanes (G a power of two <= 64).
+template <int G, typename V>
+__device__ __forceinline__ V group_incl_sum(V v) {
+  const int lg = lane_id() & (G - 1);
+#pragma unroll
+  for (int d = 1; d < G; d <<= 1) {
+    const V t = __shfl_up(v, d, G);
+    if (lg >= d) v += t;
+  }
+  return v;
+}
+
+template <int G, typename V>
+__device__ __forceinline__ V group_sum(V v) {
+#pragma unroll
+  for (int d = 1; d < G; d <<= 1) v += __shfl_xor(v, d, G);
+  return v;
+}
+
+template <int G>
+__device__ __forceinline__ bool group_all(bool p) {
+  const uint64_t m = __ballot(p);
+  if (G == 64) return m == ~0ull;
+  const int base = lane_id() & ~(G - 1);
+  const uint64_t gm = ((G == 64) ? ~0ull : ((1ull << G) - 1)) << base;
+  return (m & gm) == gm;
+}
+
+// Exclusive prefix sum over the 256 threads of a workgroup (thread order).
+// `scratch` holds kWavesPerWG entries. Returns the exclusive prefix; `total`
+// receives the workgroup total. Contains barriers: call from all threads.
+template <typename V>
+__device__ __forceinline__ V wg_excl_sum(V v, V* scratch, V& total) {
+  const V inc = group_incl_sum<kWave, V>(v);
+  const int w = threadIdx.x / kWave;
+  if (lane_id() == kWave - 1) scratch[w] = inc;
+  __syncthreads();
+  V before = 0, all = 0;
+#pragma unroll
+  for (int i = 0; i < kWavesPerWG; ++i) {
+    const V s = scratch[i];
+    before += (i < w) ? s : (V)0;
+    all += s;
+  }
+  __syncthreads();
+  total = all;
+  return before + inc - v;
+}
+
+// ------------------------------------------------------ decoupled look-back -
+
+// A tile's status word: flag in the top two bits (0 = not yet published,
+// 1 = aggregate of the tile alone, 2 = inclusive prefix), value below.
+constexpr uint64_t kFlagAgg = 1ull << 62;
+constexpr uint64_t kFlagIncl = 2ull << 62;
+constexpr uint64_t kValueMask = (1ull << 62) - 1;
+constexpr uint32_t kSpinLimit = 1u << 21;
+
+__device__ __forceinline__ void status_store(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t status_load(const uint64_t* p) {
+  return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Exclusive prefix of tile t in a device-wide scan over tiles taken in ticket
+// order. Called by all 64 lanes of one wave; returns the same value in every
+// lane. Tiles below t were handed out before t, so every predecessor is
+// running or done and each wait ends; the spin is still bounded, and on
+// exhaustion the error word is set and the partial prefix returned.
+__device__ __noinline__ uint64_t lookback_excl(uint64_t* status, uint32_t t, uint64_t agg,
+                                               uint32_t* err) {
+  const int lane = lane_id();
+  if (t == 0) {
+    if (lane == 0) status_store(status, kFlagIncl | agg);
+    return 0;
+  }
+  if (lane == 0) status_store(status + t, kFlagAgg | agg);
+  uint64_t excl = 0;
+  int64_t base = (int64_t)t - 1;
+  uint32_t spins = 0;
+  for (;;) {
+    const int64_t j = base - lane;
+    const uint64_t w = j >= 0 ? status_load(status + j) : (kFlagIncl | 0ull);
+    const uint64_t flag = w >> 62;
+    const uint64_t incl = __ballot(flag == 2);
+    const uint64_t inval = __ballot(flag == 0);
+    const int first = incl ? (int)__ffsll((long long)incl) - 1 : 64;
+    const uint64_t need = first >= 63 ? ~0ull : ((2ull << first) - 1);
+    if (inval & need) {
+      if (++spins > kSpinLimit) {
+        if (lane == 0) atomicOr(err, 1u);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+      continue;
+    }
+    uint64_t v = lane <= first ? (w & kValueMask) : 0ull;
+    v = group_sum<kWave, uint64_t>(v);
+    excl += v;
+    if (first < 64) break;
+    base -= 64;
+  }
+  if (lane == 0) status_store(status + t, kFlagIncl | ((excl + agg) & kValueMask));
+  return excl;
+}
+
+}  // namespace szx

@@ -1,0 +1,82 @@
+// szx_layout.hpp -- stream section offsets, workspace layout and the launch
+// job shared by the host API and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace szx {
+
+__host__ __device__ inline uint64_t align16(uint64_t x) { return (x + 15u) & ~(uint64_t)15u; }
+__host__ __device__ inline uint64_t align256(uint64_t x) { return (x + 255u) & ~(uint64_t)255u; }
+__host__ __device__ inline uint64_t cdiv(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+// Byte offsets of the sections of a stream (header at 0).
+struct Sections {
+  uint64_t state, mu, kbytes, codes, mid, total;
+};
+
+__host__ __device__ inline Sections sections(uint64_t nblk, uint64_t n_nc, uint64_t w, uint64_t b,
+                                             uint64_t mid_total) {
+  Sections s;
+  s.state = 96;
+  s.mu = align16(s.state + (nblk + 7) / 8);
+  s.kbytes = align16(s.mu + nblk * w);
+  s.codes = align16(s.kbytes + n_nc);
+  s.mid = align16(s.codes + n_nc * (b / 4));
+  s.total = s.mid + mid_total;
+  return s;
+}
+
+// Device-side counters at the start of the workspace (256 bytes reserved).
+struct Counters {
+  uint32_t tick_cls;   // tile tickets of the classification pass
+  uint32_t tick_enc;   // tile tickets of the encoding pass
+  uint32_t tick_dec;   // tile tickets of the decoding pass
+  uint32_t err;        // nonzero: a bounded wait gave up
+  uint64_t klo, khi;   // totalOrder keys of the smallest / largest finite value
+  uint64_t n_nc;       // non-constant blocks (raw included)
+  uint64_t mid_total;  // mid-byte section size
+  uint64_t e_bits;     // bit pattern of the bound e in the element type
+};
+
+// Validated parameters of one call.
+struct Job {
+  uint32_t dtype, eb_mode, ndims, b;
+  uint64_t dims[4];
+  uint64_t n, nblk;
+  double eb;
+  uint32_t w;
+};
+
+// Tiles of the classification pass: one block per thread.
+constexpr uint32_t kClsTile = 256;
+
+// Blocks per tile of the encode/decode passes for block size b.
+__host__ __device__ inline uint32_t tile_blocks(uint32_t b) {
+  const uint32_t epl = b >= 512 ? b / 64 : 8;
+  const uint32_t lpb = b / epl;
+  return 256 / lpb;
+}
+
+// Workspace carve-up; every piece 256-byte aligned.
+struct WsLayout {
+  uint64_t counters, stats, rec, cls_status, enc_status, dec_rank, dec_mid, total;
+};
+
+__host__ __device__ inline WsLayout ws_layout(uint64_t nblk, uint32_t w, uint32_t b) {
+  WsLayout L;
+  const uint64_t ntile = cdiv(nblk, tile_blocks(b)) + 1;
+  const uint64_t ncls = cdiv(nblk, kClsTile) + 1;
+  L.counters = 0;
+  L.stats = 256;
+  L.rec = align256(L.stats + nblk * 2 * (uint64_t)w);
+  L.cls_status = align256(L.rec + nblk * 4);
+  L.enc_status = align256(L.cls_status + ncls * 8);
+  L.dec_rank = align256(L.enc_status + ntile * 8);
+  L.dec_mid = align256(L.dec_rank + ntile * 8);
+  L.total = align256(L.dec_mid + ntile * 8);
+  return L;
+}
+
+}  // namespace szx

@@ -1,0 +1,207 @@
+"""Python binding of the C ABI in include/szx.h (argument marshalling only).
+
+PyTorch provides device memory and streams; every step of compression and
+decompression runs in the HIP kernels of ``libszx.so``. There is no fallback:
+if the library or a GPU is missing, these functions raise.
+"""
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libszx.so")
+
+SZ_F32, SZ_F64 = 0, 1
+SZ_ABS, SZ_REL = 0, 1
+STATUS = {0: "SZ_OK", 1: "SZ_EINVAL", 2: "SZ_ENOSPC", 3: "SZ_ECORRUPT", 4: "SZ_EDEVICE",
+          5: "SZ_ENOMEM", 6: "SZ_EUNSUPPORTED"}
+HEADER_BYTES = 96
+
+
+class SzParams(ctypes.Structure):
+    _fields_ = [
+        ("dtype", ctypes.c_uint32),
+        ("ndims", ctypes.c_uint32),
+        ("dims", ctypes.c_uint64 * 4),
+        ("eb_mode", ctypes.c_uint32),
+        ("block_size", ctypes.c_uint32),
+        ("eb", ctypes.c_double),
+    ]
+
+
+class SzError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libszx.so. Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER(SzParams)
+        vp, u64 = ctypes.c_void_p, ctypes.c_uint64
+        L.sz_compress_bound.argtypes = [P]
+        L.sz_compress_bound.restype = u64
+        L.sz_workspace_size.argtypes = [P]
+        L.sz_workspace_size.restype = u64
+        L.sz_compress.argtypes = [P, vp, vp, u64, vp, vp, u64, vp]
+        L.sz_compress.restype = ctypes.c_int
+        L.sz_decompress.argtypes = [vp, u64, P, vp, u64, vp, vp, u64, vp]
+        L.sz_decompress.restype = ctypes.c_int
+        L.sz_inspect.argtypes = [vp, u64, P, ctypes.POINTER(u64)]
+        L.sz_inspect.restype = ctypes.c_int
+        L.sz_last_error.argtypes = []
+        L.sz_last_error.restype = ctypes.c_char_p
+        L.sz_timing_enable.argtypes = [ctypes.c_int]
+        L.sz_timing_enable.restype = None
+        L.sz_timing_read.argtypes = [ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_uint32), ctypes.c_uint32]
+        L.sz_timing_read.restype = ctypes.c_uint32
+        _lib = L
+    return _lib
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise SzError(rc, f"{what}: {lib().sz_last_error().decode()}")
+
+
+def make_params(dtype, dims, eb=0.0, mode="rel", block=128):
+    p = SzParams()
+    dt = torch.float32 if dtype in (torch.float32, "float32", "f32") else dtype
+    if dt == torch.float32:
+        p.dtype = SZ_F32
+    elif dt in (torch.float64, "float64", "f64"):
+        p.dtype = SZ_F64
+    else:
+        raise ValueError(f"unsupported dtype {dtype}")
+    dims = tuple(int(d) for d in dims)
+    if not 1 <= len(dims) <= 4:
+        raise ValueError("1 to 4 dims")
+    p.ndims = len(dims)
+    for i, d in enumerate(dims):
+        p.dims[i] = d
+    p.eb_mode = SZ_REL if mode == "rel" else SZ_ABS
+    p.block_size = int(block)
+    p.eb = float(eb)
+    return p
+
+
+def params_dict(p):
+    return dict(dtype=torch.float32 if p.dtype == SZ_F32 else torch.float64,
+                dims=tuple(int(p.dims[i]) for i in range(p.ndims)),
+                mode="rel" if p.eb_mode == SZ_REL else "abs",
+                block=int(p.block_size), eb=float(p.eb))
+
+
+def compress_bound(dtype, dims, eb=0.0, mode="rel", block=128):
+    return int(lib().sz_compress_bound(ctypes.byref(make_params(dtype, dims, eb, mode, block))))
+
+
+def workspace_size(dtype, dims, eb=0.0, mode="rel", block=128):
+    return int(lib().sz_workspace_size(ctypes.byref(make_params(dtype, dims, eb, mode, block))))
+
+
+def _stream_handle(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def compress(x, eb, mode="rel", block=128, dims=None, out=None, out_size=None, ws=None, stream=None):
+    """Compress the device tensor x. Returns (out, out_size): the uint8 device
+    buffer holding the stream and a 1-element uint64 device tensor with its
+    size. Asynchronous on `stream` (default: torch's current stream)."""
+    if not (x.is_cuda and x.is_contiguous() and x.dtype in (torch.float32, torch.float64)):
+        raise ValueError("x must be a contiguous float32/float64 device tensor")
+    dims = tuple(x.shape) if dims is None else tuple(dims)
+    if len(dims) == 0:
+        dims = (1,)
+    p = make_params(x.dtype, dims, eb, mode, block)
+    cap = int(lib().sz_compress_bound(ctypes.byref(p)))
+    wsz = int(lib().sz_workspace_size(ctypes.byref(p)))
+    if cap == 0 or wsz == 0:
+        raise SzError(1, "invalid parameters: " + lib().sz_last_error().decode())
+    if out is None:
+        out = torch.empty(cap, dtype=torch.uint8, device=x.device)
+    if out_size is None:
+        out_size = torch.empty(1, dtype=torch.uint64, device=x.device)
+    if ws is None:
+        ws = torch.empty(wsz, dtype=torch.uint8, device=x.device)
+    rc = lib().sz_compress(ctypes.byref(p), _ptr(x), _ptr(out), out.numel(), _ptr(out_size),
+                           _ptr(ws), ws.numel(), _stream_handle(stream))
+    _check(rc, "sz_compress")
+    return out, out_size
+
+
+def inspect(header):
+    """Parse a host copy of a stream header (bytes, numpy uint8 or CPU tensor)."""
+    if isinstance(header, torch.Tensor):
+        header = header.cpu().numpy().tobytes()
+    elif not isinstance(header, (bytes, bytearray)):
+        header = bytes(header)
+    buf = ctypes.create_string_buffer(bytes(header), len(header))
+    p = SzParams()
+    total = ctypes.c_uint64()
+    rc = lib().sz_inspect(ctypes.cast(buf, ctypes.c_void_p), len(header), ctypes.byref(p),
+                          ctypes.byref(total))
+    _check(rc, "sz_inspect")
+    d = params_dict(p)
+    d["total"] = int(total.value)
+    return d
+
+
+def decompress(data, nbytes, expected, out=None, status=None, ws=None, stream=None):
+    """Decompress the stream in the uint8 device tensor `data` (nbytes bytes).
+    `expected`: dict with dtype, dims, block (e.g. from inspect()). Returns
+    (out, status): the values and a 1-element uint32 device tensor (0 = ok,
+    3 = corrupt stream). Asynchronous on `stream`."""
+    p = make_params(expected["dtype"], expected["dims"], expected.get("eb", 0.0),
+                    expected.get("mode", "rel"), expected["block"])
+    wsz = int(lib().sz_workspace_size(ctypes.byref(p)))
+    if wsz == 0:
+        raise SzError(1, "invalid parameters: " + lib().sz_last_error().decode())
+    dt = torch.float32 if p.dtype == SZ_F32 else torch.float64
+    n = 1
+    for d in expected["dims"]:
+        n *= int(d)
+    if out is None:
+        out = torch.empty(n, dtype=dt, device=data.device)
+    if status is None:
+        status = torch.empty(1, dtype=torch.uint32, device=data.device)
+    if ws is None:
+        ws = torch.empty(wsz, dtype=torch.uint8, device=data.device)
+    rc = lib().sz_decompress(_ptr(data), int(nbytes), ctypes.byref(p), _ptr(out), out.numel() * out.element_size(),
+                             _ptr(status), _ptr(ws), ws.numel(), _stream_handle(stream))
+    _check(rc, "sz_decompress")
+    return out, status
+
+
+def timing_enable(on=True):
+    lib().sz_timing_enable(1 if on else 0)
+
+
+def timing_read(cap=32):
+    """{kernel name: (launches, total ms)} since the last read (synchronises)."""
+    names = (ctypes.c_char_p * cap)()
+    ms = (ctypes.c_double * cap)()
+    cnt = (ctypes.c_uint32 * cap)()
+    m = lib().sz_timing_read(names, ms, cnt, cap)
+    return {names[i].decode(): (int(cnt[i]), float(ms[i])) for i in range(m)}
+
+
+def to_host_stream(out, out_size):
+    """Synchronise and return the compressed stream as bytes."""
+    n = int(out_size.cpu().view(torch.int64).item())
+    return out[:n].cpu().numpy().tobytes()

@@ -1,0 +1,195 @@
+"""Parity of the HIP path with the CPU oracle, through the C ABI.
+
+Compressed streams must equal the oracle's byte for byte; decompressed values
+must equal the oracle's bit for bit. Cases span several tiles with ragged
+tails, every block size, both element types, both bound modes, and the
+degenerate inputs of the method (empty, constant, raw, zero bound).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import szref
+import streamfmt as sf
+from gpu_util import first_diff, gpu_compress, gpu_decompress, gpu_roundtrip, same_bits
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2201_13020_amd import szx
+    szx.lib()  # fails loudly if the HIP library is missing
+
+
+def check_parity(x, eb, mode="rel", block=128, label=""):
+    print(f"[parity] {label} n={x.size} dtype={x.dtype} eb={eb} mode={mode} b={block}", flush=True)
+    ref = szref.compress(x, eb, mode, block)
+    stream, y, st = gpu_roundtrip(x, eb, mode, block)
+    assert st == 0
+    assert stream.size == ref.size, f"size {stream.size} vs oracle {ref.size}"
+    assert np.array_equal(stream, ref), f"first differing byte {first_diff(stream, ref)}"
+    yref = szref.decompress(ref)
+    assert same_bits(y, yref), f"first differing value {first_diff(y.view(np.uint8), yref.view(np.uint8))}"
+    return ref
+
+
+def smooth(n, seed, dtype=np.float32):
+    r = np.random.default_rng(seed)
+    t = np.arange(n) / max(n, 1)
+    x = np.zeros(n)
+    for _ in range(5):
+        x += np.sin(2 * np.pi * r.uniform(1, 300) * t + r.uniform(0, 6.28))
+    x += 1e-3 * r.standard_normal(n)
+    x[(t > 0.2) & (t < 0.27)] = 0.0
+    return x.astype(dtype)
+
+
+# ------------------------------------------------------ small parity grid --
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("block", [8, 16, 32, 64, 128, 256, 512, 1024])
+def test_parity_block_sizes(dtype, block):
+    x = smooth(200_003, 1, dtype)  # many tiles, ragged last block
+    for eb in [1e-2, 1e-4]:
+        check_parity(x, eb, "rel", block, "blocks")
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("eb", [1e-1, 1e-3, 1e-5, 1e-7, 0.0])
+def test_parity_error_bounds(dtype, eb):
+    x = smooth(333_331, 2, dtype)
+    check_parity(x, eb, "rel", 128, "ebs")
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_parity_abs_wide_exponents(dtype):
+    r = np.random.default_rng(3)
+    x = (r.standard_normal(100_000) * 10.0 ** r.integers(-20, 20, 100_000)).astype(dtype)
+    x[::7] = 0.0
+    for eb in [1e-25, 1e-3, 1.0]:
+        check_parity(x, eb, "abs", 128, "abs")
+
+
+def test_parity_special_values():
+    tiny = np.float32(1.4e-45)
+    big = np.finfo(np.float32).max
+    vals = [0.0, -0.0, tiny, -tiny, 1e-39, -1e-39, 1e-38, big, -big, 1.0, -1.0]
+    r = np.random.default_rng(4)
+    x = np.array(r.choice(vals, 50_000), dtype=np.float32)
+    x[1000:1300] = np.nan
+    x[5000] = np.inf
+    x[9000] = -np.inf
+    for eb in [0.0, 1e-40, 1e-3]:
+        for b in [8, 128]:
+            check_parity(x, eb, "abs", b, "special")
+    check_parity(x, 1e-3, "rel", 128, "special-rel")
+
+
+def test_parity_all_nan_and_constant():
+    x = np.full(10_000, np.nan, dtype=np.float32)
+    check_parity(x, 1e-3, "rel", 128, "all-nan")
+    x = np.full((33, 1000), 2.5, dtype=np.float64)
+    ref = check_parity(x, 1e-3, "rel", 64, "constant")
+    assert sf.parse(ref)["n_nc"] == 0
+
+
+@pytest.mark.parametrize("n", [0, 1, 7, 8, 9, 127, 128, 129, 2047, 2048, 2049, 4095])
+def test_parity_ragged_sizes(n):
+    for dtype in (np.float32, np.float64):
+        x = smooth(n, 5 + n, dtype)
+        check_parity(x, 1e-3, "rel", 128, "ragged")
+        check_parity(x, 1e-3, "rel", 8, "ragged8")
+
+
+def test_parity_multidim_metadata():
+    from paper_2201_13020_amd import synth
+    x = synth.make("cfg2", (20, 50, 50))
+    for eb in [1e-2, 1e-3, 1e-4]:
+        ref = check_parity(x, eb, "rel", 128, "cfg2-small")
+        assert sf.parse(ref)["dims"] == (20, 50, 50)
+
+
+def test_parity_ladder_and_raw_escalation():
+    """Blocks whose bound has a mantissa near 2 and mid values far from the
+    data make the first bit budget fail; the escalation must match."""
+    r = np.random.default_rng(6)
+    x = (1e6 + r.standard_normal(64 * 2000) * 1e3).astype(np.float32)
+    e = np.float32(1.9999) * np.float32(2.0 ** -3)
+    ref = check_parity(x, float(e), "abs", 64, "ladder")
+    info = sf.parse(ref)
+    ks = info["K"]
+    assert len(set(ks.tolist())) >= 2
+
+
+def test_golden_index_propagation_stream():
+    from test_oracle_pins import golden_index_propagation_stream
+    stream, want = golden_index_propagation_stream()
+    y, st = gpu_decompress(stream)
+    assert st == 0
+    assert np.array_equal(y.view(np.uint32), want)
+
+
+def test_decoder_flags_corrupt_streams():
+    x = smooth(50_000, 7)
+    ref = szref.compress(x, 1e-3, "rel", 128)
+    info = sf.parse(ref)
+    from paper_2201_13020_amd import szx
+    exp = szx.inspect(ref[:96].tobytes())
+    # bad K byte
+    c = ref.copy()
+    c[info["offsets"]["K"]] = 5
+    y, st = gpu_decompress(c, exp)
+    assert st == 3
+    # truncated stream (declared size larger than the buffer)
+    y, st = gpu_decompress(ref[: len(ref) - 10], exp)
+    assert st == 3
+    # code larger than the kept bytes: find a block with nb == 2 if any, else flip magic
+    c = ref.copy()
+    c[0] ^= 0xFF
+    y, st = gpu_decompress(c, exp)
+    assert st == 3
+    # a wrong mid_total
+    c = ref.copy()
+    c[88] ^= 1
+    y, st = gpu_decompress(c, exp)
+    assert st == 3
+    # the clean stream still decodes
+    y, st = gpu_decompress(ref, exp)
+    assert st == 0
+
+
+def test_determinism_repeated_calls():
+    x = smooth(1_000_003, 8)
+    a = gpu_roundtrip(x, 1e-3, "rel", 128)[0]
+    for _ in range(3):
+        b = gpu_roundtrip(x, 1e-3, "rel", 128)[0]
+        assert np.array_equal(a, b)
+
+
+# ------------------------------------------------- full-size workloads --
+
+def test_parity_cfg1_full():
+    from paper_2201_13020_amd import synth
+    x = synth.make("cfg1")
+    check_parity(x, 1e-3, "rel", 128, "cfg1")
+
+
+@pytest.mark.parametrize("eb", [1e-2, 1e-3, 1e-4])
+def test_parity_cfg2_full(eb):
+    from paper_2201_13020_amd import synth
+    x = synth.make("cfg2")
+    check_parity(x, eb, "rel", 128, "cfg2")
+
+
+@pytest.mark.parametrize("eb", [1e-3, 1e-5])
+def test_parity_cfg3a_full(eb):
+    from paper_2201_13020_amd import synth
+    x = synth.make("cfg3a")
+    check_parity(x, eb, "rel", 128, "cfg3a")
