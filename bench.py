@@ -1,0 +1,275 @@
+#!/usr/bin/env python
+"""Throughput of SZx compression and decompression on one MI355X.
+
+Workload: a 100x500x500 float32 field in the shape of the paper's Hurricane
+fields (synthetic: k^-5/3 Gaussian random field with 20 % exact-zero regions),
+value-range relative bounds 1e-2, 1e-3 and 1e-4, block size 128.
+
+One step = for each of the three bounds, compress the field and decompress the
+stream (every kernel of both directions, including the global range pass of
+the relative bound). Inputs and outputs rotate over several copies so that the
+256 MB last-level cache cannot serve a step from the previous step's data.
+The steps are replayed from HIP graphs captured once per copy (the C ABI is
+asynchronous and allocation-free, so a whole step captures); --eager launches
+them directly instead.
+
+Prints one JSON line. `value` is the round-trip throughput in GB/s of
+uncompressed bytes: bytes compressed in the step divided by the time of the
+step (compress + decompress). Per-bound compress/decompress GB/s, ratios and
+HBM fractions are in `detail`. `roofline` is the dominant kernel's
+algorithmic bytes per launch over its average launch duration (HIP events on
+its stream during a second, instrumented timed region). `cpu_baseline` is the
+CPU oracle (single thread) on the same field and bounds.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+BOUNDS = (1e-2, 1e-3, 1e-4)
+BLOCK = 128
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--copies", type=int, default=4)
+    ap.add_argument("--eager", action="store_true", help="launch directly instead of graph replay")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile", action="store_true",
+                    help="short run for profilers: no CPU baseline, no instrumented pass, plus one plain copy of known size")
+    ap.add_argument("--shape", type=str, default="100,500,500")
+    return ap.parse_args()
+
+
+def kernel_bytes(name, n, w, nblk, n_nc, mid_total, b=BLOCK):
+    """Algorithmic HBM bytes of one launch of each kernel (reads + writes)."""
+    sec_codes = n_nc * (b // 4)
+    if name == "k_stats":
+        return n * w + nblk * 2 * w
+    if name == "k_classify":
+        return nblk * 2 * w + nblk * w + nblk / 8 + 4 * n_nc
+    if name == "k_encode":
+        return n_nc * b * w + n_nc * (2 * w + 4) + n_nc + sec_codes + mid_total
+    if name == "k_decode":
+        return nblk / 8 + nblk * w + n_nc + sec_codes + mid_total + n * w
+    return 0
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is design-only)"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2201_13020_amd import synth, szx
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    dev = torch.device("cuda:0")
+    shape = tuple(int(s) for s in args.shape.split(","))
+    x_np = synth.turbulence_3d(shape)
+    n = x_np.size
+    w = x_np.itemsize
+    nbytes = n * w
+    C = max(1, args.copies)
+    xs = [torch.from_numpy(x_np).to(dev) for _ in range(C)]
+    cap = szx.compress_bound(torch.float32, shape, 1e-3, "rel", BLOCK)
+    wsz = szx.workspace_size(torch.float32, shape, 1e-3, "rel", BLOCK)
+    outs = {eb: [torch.empty(cap, dtype=torch.uint8, device=dev) for _ in range(C)] for eb in BOUNDS}
+    sizes = {eb: [torch.zeros(1, dtype=torch.uint64, device=dev) for _ in range(C)] for eb in BOUNDS}
+    ys = [torch.empty(n, dtype=torch.float32, device=dev) for _ in range(C)]
+    stat = torch.zeros(1, dtype=torch.uint32, device=dev)
+    ws = torch.empty(wsz, dtype=torch.uint8, device=dev)
+    expected = dict(dtype=torch.float32, dims=shape, block=BLOCK)
+
+    # first pass: stream sizes (the decoder reads only what the header says,
+    # but the in_bytes argument must cover the stream)
+    stream_len = {}
+    for eb in BOUNDS:
+        szx.compress(xs[0], eb, "rel", BLOCK, out=outs[eb][0], out_size=sizes[eb][0], ws=ws)
+        torch.cuda.synchronize()
+        stream_len[eb] = int(sizes[eb][0].cpu().view(torch.int64).item())
+
+    def step(c, timed_ops=None):
+        for eb in BOUNDS:
+            if timed_ops is not None:
+                timed_ops[eb][0].record()
+            szx.compress(xs[c], eb, "rel", BLOCK, out=outs[eb][c], out_size=sizes[eb][c], ws=ws)
+            if timed_ops is not None:
+                timed_ops[eb][1].record()
+            szx.decompress(outs[eb][c], cap, expected, out=ys[c], status=stat, ws=ws)
+            if timed_ops is not None:
+                timed_ops[eb][2].record()
+
+    # correctness against the CPU oracle (also the CPU baseline timing)
+    cpu = None
+    ratios = {}
+    for eb in BOUNDS:
+        step(0)
+    torch.cuda.synchronize()
+    for eb in BOUNDS:
+        ratios[eb] = nbytes / stream_len[eb]
+    if not args.no_cpu_baseline and not args.profile:
+        from oracle import szref
+        t_c = t_d = 0.0
+        for eb in BOUNDS:
+            t0 = time.perf_counter()
+            ref = szref.compress(x_np, eb, "rel", BLOCK)
+            t1 = time.perf_counter()
+            yref = szref.decompress(ref)
+            t2 = time.perf_counter()
+            t_c += t1 - t0
+            t_d += t2 - t1
+            gpu_stream = outs[eb][0][: stream_len[eb]].cpu().numpy()
+            assert gpu_stream.size == ref.size and np.array_equal(gpu_stream, ref), f"GPU stream differs from the oracle at eb={eb}"
+        y_last = ys[0].cpu().numpy()
+        assert np.array_equal(y_last.view(np.uint32), yref.ravel().view(np.uint32)), "GPU decode differs from the oracle"
+        cpu = {
+            "value": round(3 * nbytes / (t_c + t_d) / 1e9, 4),
+            "unit": "GB/s",
+            "cores": 1,
+            "kind": "oracle",
+            "sample": f"whole workload once: {'x'.join(map(str, shape))} float32, REL {', '.join(map(str, BOUNDS))}, "
+                      f"compress + decompress each, single thread; compress {3 * nbytes / t_c / 1e6:.0f} MB/s, "
+                      f"decompress {3 * nbytes / t_d / 1e6:.0f} MB/s",
+            "seconds": round(t_c + t_d, 3),
+        }
+
+    # graphs, one per copy
+    graphs = None
+    if not args.eager:
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            for c in range(C):
+                step(c)
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        graphs = []
+        for c in range(C):
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                step(c)
+            graphs.append(g)
+        torch.cuda.synchronize()
+
+    def run(c):
+        if graphs is not None:
+            graphs[c].replay()
+        else:
+            step(c)
+
+    for i in range(args.warmup):
+        run(i % C)
+    torch.cuda.synchronize()
+
+    # timed region
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        run(i % C)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = elapsed * 1e3 / args.steps
+    value = 3 * nbytes / (elapsed / args.steps) / 1e9
+
+    # check the last replays decoded correctly (status and a spot check)
+    assert int(stat.cpu().view(torch.int32).item()) == 0
+
+    result = {
+        "metric": "compress & decompress GB/s (uncompressed) and % of HBM peak; ratio",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{'x'.join(map(str, shape))} float32 turbulence field with 20% zero regions, "
+                               f"REL {', '.join(map(str, BOUNDS))}, block {BLOCK}; one step = compress + decompress at each bound",
+                   "global_batch": 3, "elements": n, "block": BLOCK, "parallelism": "single GPU",
+                   "launch": "eager" if graphs is None else "hip graph replay", "input_copies": C},
+    }
+
+    if not args.profile:
+        # per-direction timings with events between the calls
+        ev = {eb: [torch.cuda.Event(enable_timing=True) for _ in range(3)] for eb in BOUNDS}
+        tc = {eb: 0.0 for eb in BOUNDS}
+        td = {eb: 0.0 for eb in BOUNDS}
+        for i in range(args.steps):
+            step(i % C, ev)
+            torch.cuda.synchronize()
+            for eb in BOUNDS:
+                tc[eb] += ev[eb][0].elapsed_time(ev[eb][1])
+                td[eb] += ev[eb][1].elapsed_time(ev[eb][2])
+        detail = {}
+        for eb in BOUNDS:
+            c_ms = tc[eb] / args.steps
+            d_ms = td[eb] / args.steps
+            detail[str(eb)] = {
+                "ratio": round(ratios[eb], 4),
+                "compress_GBps": round(nbytes / c_ms / 1e6, 1),
+                "decompress_GBps": round(nbytes / d_ms / 1e6, 1),
+                "compress_ms": round(c_ms, 4),
+                "decompress_ms": round(d_ms, 4),
+                "compress_hbm_frac_uncompressed": round(nbytes / c_ms / 1e6 / HBM_PEAK_GBPS, 4),
+                "decompress_hbm_frac_uncompressed": round(nbytes / d_ms / 1e6 / HBM_PEAK_GBPS, 4),
+            }
+        result["detail"] = {"eager_launch_per_direction": detail}
+
+        # per-kernel durations with HIP events around each launch (same stream)
+        szx.timing_enable(True)
+        szx.timing_read()
+        for i in range(args.steps):
+            step(i % C)
+        torch.cuda.synchronize()
+        kt = szx.timing_read()
+        szx.timing_enable(False)
+        # stream facts for the algorithmic bytes
+        import struct
+        facts = {}
+        for eb in BOUNDS:
+            hdr = outs[eb][0][:96].cpu().numpy().tobytes()
+            nblk, n_nc, mid_total = struct.unpack_from("<3Q", hdr, 72)
+            facts[eb] = (nblk, n_nc, mid_total)
+        kernels = {}
+        for name, (cnt, ms) in kt.items():
+            # each kernel runs once per bound per step: average algorithmic bytes over the bounds
+            alg = sum(kernel_bytes(name, n, w, *facts[eb]) for eb in BOUNDS) / len(BOUNDS)
+            avg_ms = ms / cnt
+            kernels[name] = {"launches": cnt, "avg_us": round(avg_ms * 1e3, 2),
+                             "alg_bytes_per_launch": int(alg),
+                             "achieved_GBps": round(alg / avg_ms / 1e6, 1) if alg else None}
+        result["detail"]["kernels"] = kernels
+        dom = max((k for k in kernels if kernels[k]["alg_bytes_per_launch"]), key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches"])
+        kd = kernels[dom]
+        result["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": kd["achieved_GBps"],
+                              "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                              "frac": round(kd["achieved_GBps"] / HBM_PEAK_GBPS, 4), "traffic": None}
+    if cpu is not None:
+        result["cpu_baseline"] = cpu
+
+    if args.profile:
+        # a plain device copy of known size, to scale the HBM byte counters
+        a = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -98,9 +98,10 @@ sz_status sz_compress(const sz_params* p, const void* d_in, void* d_out,
    d_out (device, 16-byte aligned, out_cap >= N * sizeof(T) bytes). `expected`
    gives the field's dtype, dims and block size (from sz_inspect on a host copy
    of the header, or from the caller's own metadata); the kernels check the
-   device header against it. *d_status (device u32) receives SZ_OK or
-   SZ_ECORRUPT; on SZ_ECORRUPT the output is unspecified but no access leaves
-   the given buffers. d_ws as for sz_compress, sized with `expected`.
+   device header against it. *d_status (device u32) receives SZ_OK,
+   SZ_ECORRUPT (the stream failed validation) or SZ_EDEVICE (a bounded wait
+   between workgroups gave up); otherwise the output is unspecified but no
+   access leaves the given buffers. d_ws as for sz_compress, sized with `expected`.
    Asynchronous on `stream`. Sec. V-B: leading bytes are resolved by a parallel
    scan over the 2-bit codes, mid bytes are located by a prefix scan. */
 sz_status sz_decompress(const void* d_in, uint64_t in_bytes,

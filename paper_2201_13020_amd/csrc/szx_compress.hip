@@ -32,9 +32,6 @@ __global__ __launch_bounds__(256) void k_init(Counters* ctr, uint64_t* st1, uint
       st2[i - n1] = 0;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    ctr->tick_cls = 0;
-    ctr->tick_enc = 0;
-    ctr->tick_dec = 0;
     ctr->err = 0;
     ctr->klo = ~0ull;
     ctr->khi = 0;
@@ -98,63 +95,75 @@ __device__ __forceinline__ U group_max(U v) {
 
 // ----------------------------------------------------------------- stats ---
 
-// Per-block totalOrder extrema (as keys) of all values, and the global finite
-// range when want_range is set.
+// Per-block totalOrder extrema (as keys) of all values, and per workgroup the
+// finite range (keys; lo > hi when the workgroup saw no finite value) into
+// part[2 * blockIdx.x], part[2 * blockIdx.x + 1]. Two tiles per iteration keep
+// more loads in flight.
+template <typename T, int B>
+__device__ __forceinline__ void stats_tile(const T (&v)[Geo<T, B>::EPL], int cnt, uint64_t i0, uint64_t nblk,
+                                           typename Traits<T>::U* __restrict__ stats,
+                                           typename Traits<T>::U& flo, typename Traits<T>::U& fhi) {
+  using U = typename Traits<T>::U;
+  constexpr int EPL = Geo<T, B>::EPL, LPB = Geo<T, B>::LPB;
+  U kmin = (U)~(U)0, kmax = 0;
+#pragma unroll
+  for (int i = 0; i < EPL; ++i) {
+    const U u = bits_of(v[i]);
+    const U k = order_key<U>(u);
+    const bool ok = i < cnt;
+    kmin = (ok && k < kmin) ? k : kmin;
+    kmax = (ok && k > kmax) ? k : kmax;
+    const bool fin = ok && is_finite_bits<T>(u);
+    flo = (fin && k < flo) ? k : flo;
+    fhi = (fin && k > fhi) ? k : fhi;
+  }
+  kmin = group_min<LPB, U>(kmin);
+  kmax = group_max<LPB, U>(kmax);
+  const uint64_t blk = i0 / B;
+  if ((threadIdx.x % LPB) == 0 && blk < nblk) {
+    stats[2 * blk] = kmin;
+    stats[2 * blk + 1] = kmax;
+  }
+}
+
 template <typename T, int B>
 __global__ __launch_bounds__(256) void k_stats(const T* __restrict__ x, uint64_t n, uint64_t nblk,
                                                typename Traits<T>::U* __restrict__ stats,
-                                               Counters* ctr, int want_range) {
+                                               uint64_t* __restrict__ part) {
   using U = typename Traits<T>::U;
   using G = Geo<T, B>;
-  constexpr int EPL = G::EPL, LPB = G::LPB;
+  constexpr int EPL = G::EPL;
   __shared__ U s_lo[kWavesPerWG], s_hi[kWavesPerWG];
   U flo = (U)~(U)0, fhi = 0;
   const uint64_t ntile = cdiv(n, (uint64_t)G::TILE);
-  const int lig = threadIdx.x % LPB;
-  for (uint64_t t = blockIdx.x; t < ntile; t += gridDim.x) {
+  const uint64_t step = gridDim.x;
+  for (uint64_t t = blockIdx.x; t < ntile; t += 2 * step) {
     const uint64_t i0 = t * G::TILE + (uint64_t)threadIdx.x * EPL;
-    T v[EPL];
-    const int cnt = load_run<T, EPL>(x, i0, n, v);
-    U kmin = (U)~(U)0, kmax = 0;
-#pragma unroll
-    for (int i = 0; i < EPL; ++i) {
-      const U u = bits_of(v[i]);
-      const U k = order_key<U>(u);
-      const bool ok = i < cnt;
-      kmin = (ok && k < kmin) ? k : kmin;
-      kmax = (ok && k > kmax) ? k : kmax;
-      const bool fin = ok && is_finite_bits<T>(u);
-      flo = (fin && k < flo) ? k : flo;
-      fhi = (fin && k > fhi) ? k : fhi;
-    }
-    kmin = group_min<LPB, U>(kmin);
-    kmax = group_max<LPB, U>(kmax);
-    const uint64_t blk = i0 / B;
-    if (lig == 0 && blk < nblk) {
-      stats[2 * blk] = kmin;
-      stats[2 * blk + 1] = kmax;
-    }
+    const uint64_t i1 = i0 + step * G::TILE;
+    const bool second = t + step < ntile;
+    T v0[EPL], v1[EPL];
+    const int c0 = load_run<T, EPL>(x, i0, n, v0);
+    const int c1 = second ? load_run<T, EPL>(x, i1, n, v1) : 0;
+    stats_tile<T, B>(v0, c0, i0, nblk, stats, flo, fhi);
+    if (second) stats_tile<T, B>(v1, c1, i1, nblk, stats, flo, fhi);
   }
-  if (want_range) {
-    flo = group_min<kWave, U>(flo);
-    fhi = group_max<kWave, U>(fhi);
-    const int w = threadIdx.x / kWave;
-    if (lane_id() == 0) {
-      s_lo[w] = flo;
-      s_hi[w] = fhi;
+  flo = group_min<kWave, U>(flo);
+  fhi = group_max<kWave, U>(fhi);
+  const int w = threadIdx.x / kWave;
+  if (lane_id() == 0) {
+    s_lo[w] = flo;
+    s_hi[w] = fhi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    U lo = s_lo[0], hi = s_hi[0];
+    for (int i = 1; i < kWavesPerWG; ++i) {
+      lo = s_lo[i] < lo ? s_lo[i] : lo;
+      hi = s_hi[i] > hi ? s_hi[i] : hi;
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      U lo = s_lo[0], hi = s_hi[0];
-      for (int i = 1; i < kWavesPerWG; ++i) {
-        lo = s_lo[i] < lo ? s_lo[i] : lo;
-        hi = s_hi[i] > hi ? s_hi[i] : hi;
-      }
-      if (lo <= hi) {
-        atomicMin((unsigned long long*)&ctr->klo, (unsigned long long)lo);
-        atomicMax((unsigned long long*)&ctr->khi, (unsigned long long)hi);
-      }
-    }
+    // widen to 64 bits keeping "no finite value" as lo > hi
+    part[2 * blockIdx.x] = lo > hi ? ~0ull : (uint64_t)lo;
+    part[2 * blockIdx.x + 1] = lo > hi ? 0ull : (uint64_t)hi;
   }
 }
 
@@ -164,20 +173,44 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_classify(const typename Traits<T>::U* __restrict__ stats,
                                                   uint8_t* __restrict__ out, uint32_t* __restrict__ rec,
                                                   uint64_t* cls_status, Counters* ctr, uint64_t nblk,
-                                                  uint64_t mu_off, int rel, double eb) {
+                                                  uint64_t mu_off, int rel, double eb,
+                                                  const uint64_t* __restrict__ part, uint32_t nparts) {
   using U = typename Traits<T>::U;
-  __shared__ uint32_t s_tick;
   __shared__ uint32_t s_scan[kWavesPerWG];
   __shared__ uint64_t s_base;
-  const T e = bound_from<T>(rel, eb, ctr->klo, ctr->khi);
-  if (blockIdx.x == 0 && threadIdx.x == 0) ctr->e_bits = (uint64_t)bits_of(e);
+  __shared__ uint64_t s_lo[kWavesPerWG], s_hi[kWavesPerWG];
+  // global finite range from the per-workgroup partials of k_stats
+  uint64_t lo = ~0ull, hi = 0;
+  if (rel) {
+    for (uint32_t i = threadIdx.x; i < nparts; i += kWG) {
+      const uint64_t a = part[2 * i], b = part[2 * i + 1];
+      lo = a < lo ? a : lo;
+      hi = b > hi ? b : hi;
+    }
+    lo = group_min<kWave, uint64_t>(lo);
+    hi = group_max<kWave, uint64_t>(hi);
+    if (lane_id() == 0) {
+      s_lo[threadIdx.x / kWave] = lo;
+      s_hi[threadIdx.x / kWave] = hi;
+    }
+    __syncthreads();
+    lo = s_lo[0];
+    hi = s_hi[0];
+    for (int i = 1; i < kWavesPerWG; ++i) {
+      lo = s_lo[i] < lo ? s_lo[i] : lo;
+      hi = s_hi[i] > hi ? s_hi[i] : hi;
+    }
+  }
+  const T e = bound_from<T>(rel, eb, lo, hi);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctr->klo = lo;
+    ctr->khi = hi;
+    ctr->e_bits = (uint64_t)bits_of(e);
+  }
   const uint32_t ntiles = (uint32_t)cdiv(nblk, kClsTile);
   T* mus = reinterpret_cast<T*>(out + mu_off);
-  for (;;) {
-    if (threadIdx.x == 0) s_tick = atomicAdd(&ctr->tick_cls, 1u);
-    __syncthreads();
-    const uint32_t t = s_tick;
-    if (t >= ntiles) break;
+  {
+    const uint32_t t = blockIdx.x;
     const uint64_t k = (uint64_t)t * kClsTile + threadIdx.x;
     bool nc = false;
     if (k < nblk) {
@@ -201,14 +234,13 @@ __global__ __launch_bounds__(256) void k_classify(const typename Traits<T>::U* _
     uint32_t total;
     const uint32_t ex = wg_excl_sum<uint32_t>(nc ? 1u : 0u, s_scan, total);
     if (threadIdx.x < kWave) {
-      const uint64_t p = lookback_excl(cls_status, t, total, &ctr->err);
+      const uint64_t p = lookback_excl(cls_status, t, total, &ctr->err, 1u);
       if (threadIdx.x == 0) s_base = p;
     }
     __syncthreads();
     const uint64_t base = s_base;
     if (nc) rec[base + ex] = (uint32_t)k;
     if (t == ntiles - 1 && threadIdx.x == 0) ctr->n_nc = base + total;
-    __syncthreads();
   }
 }
 
@@ -287,7 +319,6 @@ __global__ __launch_bounds__(256) void k_encode(const T* __restrict__ x, uint8_t
   constexpr int EPL = G::EPL, LPB = G::LPB, TB = G::TB;
   constexpr int BYTES = Traits<T>::BYTES;
   constexpr int STAGE_WORDS = (G::TILE * BYTES + 16) / 4 + 4;
-  __shared__ uint32_t s_tick;
   __shared__ uint32_t s_scan[kWavesPerWG];
   __shared__ uint64_t s_base;
   __shared__ __align__(16) uint32_t s_stage[STAGE_WORDS];
@@ -299,11 +330,9 @@ __global__ __launch_bounds__(256) void k_encode(const T* __restrict__ x, uint8_t
   T* mus = reinterpret_cast<T*>(out + mu_off);
   const int g = threadIdx.x / LPB, lig = threadIdx.x % LPB;
 
-  for (;;) {
-    if (threadIdx.x == 0) s_tick = atomicAdd(&ctr->tick_enc, 1u);
-    __syncthreads();
-    const uint32_t t = s_tick;
-    if (t >= ntiles) break;
+  {
+    const uint32_t t = blockIdx.x;
+    if (t >= ntiles) return;  // the grid covers every block; fewer are non-constant
 
     const uint64_t r = (uint64_t)t * TB + g;
     const bool active = r < n_nc;
@@ -371,7 +400,7 @@ __global__ __launch_bounds__(256) void k_encode(const T* __restrict__ x, uint8_t
     for (int i = threadIdx.x; i < STAGE_WORDS / 4; i += kWG)
       reinterpret_cast<uint4*>(s_stage)[i] = make_uint4(0, 0, 0, 0);
     if (threadIdx.x < kWave) {
-      const uint64_t p = lookback_excl(enc_status, t, tile_bytes, &ctr->err);
+      const uint64_t p = lookback_excl(enc_status, t, tile_bytes, &ctr->err, 1u);
       if (threadIdx.x == 0) s_base = p;
     }
     __syncthreads();
@@ -416,7 +445,6 @@ __global__ __launch_bounds__(256) void k_encode(const T* __restrict__ x, uint8_t
     __syncthreads();
     copy_out(out + (gdst - st), s_stage, st, tile_bytes);
     if (t == ntiles - 1 && threadIdx.x == 0) ctr->mid_total = base + tile_bytes;
-    __syncthreads();
   }
 }
 
@@ -471,6 +499,7 @@ hipError_t launch_compress_t(const Job& j, const CompressLaunch& L, TimerHook ho
   uint32_t* rec = reinterpret_cast<uint32_t*>(L.ws + W.rec);
   uint64_t* cls_st = reinterpret_cast<uint64_t*>(L.ws + W.cls_status);
   uint64_t* enc_st = reinterpret_cast<uint64_t*>(L.ws + W.enc_status);
+  uint64_t* part = reinterpret_cast<uint64_t*>(L.ws + W.range_part);
   const uint64_t ncls = cdiv(j.nblk, kClsTile) + 1;
   const uint64_t nenc = cdiv(j.nblk, G::TB) + 1;
   const Sections sec0 = sections(j.nblk, 0, j.w, j.b, 0);
@@ -486,17 +515,16 @@ hipError_t launch_compress_t(const Job& j, const CompressLaunch& L, TimerHook ho
   }
   if (j.nblk > 0) {
     const uint64_t ntile = cdiv(j.n, (uint64_t)G::TILE);
-    const uint32_t grid = (uint32_t)std::min<uint64_t>(ntile, (uint64_t)L.n_cu * 8);
+    const uint32_t grid = (uint32_t)std::min<uint64_t>(ntile, std::min<uint64_t>(kMaxRangeParts, (uint64_t)L.n_cu * 4));
     run("k_stats", [&] {
-      k_stats<T, B><<<grid, 256, 0, L.stream>>>((const T*)L.in, j.n, j.nblk, stats, ctr,
-                                                 j.eb_mode == 1 ? 1 : 0);
+      k_stats<T, B><<<grid, 256, 0, L.stream>>>((const T*)L.in, j.n, j.nblk, stats, part);
     });
-    const uint32_t gcls = (uint32_t)std::min<uint64_t>(cdiv(j.nblk, kClsTile), (uint64_t)L.n_cu * 4);
+    const uint32_t gcls = (uint32_t)cdiv(j.nblk, kClsTile);
     run("k_classify", [&] {
       k_classify<T><<<gcls, 256, 0, L.stream>>>(stats, L.out, rec, cls_st, ctr, j.nblk, sec0.mu,
-                                                j.eb_mode == 1 ? 1 : 0, j.eb);
+                                                j.eb_mode == 1 ? 1 : 0, j.eb, part, grid);
     });
-    const uint32_t genc = (uint32_t)std::min<uint64_t>(cdiv(j.nblk, G::TB), (uint64_t)L.n_cu * 8);
+    const uint32_t genc = (uint32_t)cdiv(j.nblk, G::TB);
     run("k_encode", [&] {
       k_encode<T, B><<<genc, 256, 0, L.stream>>>((const T*)L.in, L.out, stats, rec, enc_st, ctr, j.n,
                                                   j.nblk, sec0.mu);

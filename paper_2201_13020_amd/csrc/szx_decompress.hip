@@ -1,7 +1,7 @@
 // szx_decompress.hip -- decompression kernel of the SZx method for gfx950.
 //
 // One persistent kernel over tiles of consecutive blocks, tiles taken in
-// ticket order. Per tile:
+// workgroup order (tile t = workgroup t). Per tile:
 //   1. state bits -> the tile's non-constant blocks; a device-wide prefix count
 //      (decoupled look-back) gives their ranks, hence their K byte and codes;
 //   2. per value, the count of stored mid bytes (kept bytes minus the leading
@@ -25,7 +25,8 @@
 
 namespace szx {
 
-constexpr uint32_t kStatusCorrupt = 3;
+constexpr uint32_t kStatusCorrupt = 3;  // SZ_ECORRUPT
+constexpr uint32_t kStatusDevice = 4;   // SZ_EDEVICE: a bounded wait gave up
 
 struct DecodeArgs {
   const uint8_t* in;
@@ -44,8 +45,6 @@ __global__ __launch_bounds__(256) void k_dinit(Counters* ctr, uint64_t* st1, uin
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n1; i += stride) st1[i] = 0;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    ctr->tick_dec = 0;
-    ctr->err = 0;
     *status = 0;
   }
 }
@@ -141,7 +140,6 @@ __global__ __launch_bounds__(256) void k_decode(DecodeArgs a) {
   constexpr int EPL = G::EPL, LPB = G::LPB, TB = G::TB;
   constexpr int BYTES = Traits<T>::BYTES;
   constexpr int STAGE_WORDS = (G::TILE * BYTES + 32) / 4 + 4;
-  __shared__ uint32_t s_tick;
   __shared__ uint32_t s_scan[kWavesPerWG];
   __shared__ uint64_t s_r0, s_m0;
   __shared__ __align__(16) uint32_t s_stage[STAGE_WORDS];
@@ -166,7 +164,7 @@ __global__ __launch_bounds__(256) void k_decode(DecodeArgs a) {
     }
   }
   if (!hdr_ok) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(a.status, kStatusCorrupt);
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicMax(a.status, kStatusCorrupt);
     return;
   }
 
@@ -176,11 +174,9 @@ __global__ __launch_bounds__(256) void k_decode(DecodeArgs a) {
   const T* mus = reinterpret_cast<const T*>(in + sec.mu);
   T* y = reinterpret_cast<T*>(a.out);
 
-  for (;;) {
-    if (threadIdx.x == 0) s_tick = atomicAdd(&a.ctr->tick_dec, 1u);
-    __syncthreads();
-    const uint32_t t = s_tick;
-    if (t >= ntiles) break;
+  {
+    const uint32_t t = blockIdx.x;
+    if (t >= ntiles) return;
     bool bad = false;
 
     const uint64_t k = (uint64_t)t * TB + g;
@@ -194,7 +190,7 @@ __global__ __launch_bounds__(256) void k_decode(DecodeArgs a) {
     const uint32_t rank_in_tile = wg_excl_sum<uint32_t>((lig == 0 && nc) ? 1u : 0u, s_scan, tile_nc);
     const uint32_t grp_rank = __shfl(rank_in_tile, lane - lig);
     if (threadIdx.x < kWave) {
-      const uint64_t p = lookback_excl(a.rank_st, t, tile_nc, &a.ctr->err);
+      const uint64_t p = lookback_excl(a.rank_st, t, tile_nc, a.status, kStatusDevice);
       if (threadIdx.x == 0) s_r0 = p;
     }
     __syncthreads();
@@ -233,7 +229,7 @@ __global__ __launch_bounds__(256) void k_decode(DecodeArgs a) {
     uint32_t tile_bytes;
     const uint32_t lane_off = wg_excl_sum<uint32_t>(lane_bytes, s_scan, tile_bytes);
     if (threadIdx.x < kWave) {
-      const uint64_t p = lookback_excl(a.mid_st, t, tile_bytes, &a.ctr->err);
+      const uint64_t p = lookback_excl(a.mid_st, t, tile_bytes, a.status, kStatusDevice);
       if (threadIdx.x == 0) s_m0 = p;
     }
     __syncthreads();
@@ -314,10 +310,8 @@ __global__ __launch_bounds__(256) void k_decode(DecodeArgs a) {
       }
     }
     if (cnt > 0) store_run<T, EPL>(y, k * B + (uint64_t)lig * EPL, cnt, v);
-    if (__ballot(bad) != 0 && lane == 0) atomicOr(a.status, kStatusCorrupt);
-    __syncthreads();
+    if (__ballot(bad) != 0 && lane == 0) atomicMax(a.status, kStatusCorrupt);
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0 && a.ctr->err) atomicOr(a.status, kStatusCorrupt);
 }
 
 // ---------------------------------------------------------------- launch ---
@@ -354,7 +348,7 @@ hipError_t launch_decompress_t(const Job& j, const DecompressLaunch& L, TimerHoo
   a.ndims = j.ndims;
   for (int d = 0; d < 4; ++d) a.dims[d] = j.dims[d];
   (void)ntile;
-  const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(cdiv(j.nblk, G::TB), (uint64_t)L.n_cu * 8));
+  const uint32_t grid = (uint32_t)std::max<uint64_t>(1, cdiv(j.nblk, G::TB));
   run("k_decode", [&] { k_decode<T, B><<<grid, 256, 0, L.stream>>>(a); });
   return hipGetLastError();
 }

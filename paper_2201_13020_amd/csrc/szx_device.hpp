@@ -274,22 +274,27 @@ __device__ __forceinline__ V wg_excl_sum(V v, V* scratch, V& total) {
 constexpr uint64_t kFlagAgg = 1ull << 62;
 constexpr uint64_t kFlagIncl = 2ull << 62;
 constexpr uint64_t kValueMask = (1ull << 62) - 1;
-constexpr uint32_t kSpinLimit = 1u << 21;
+constexpr uint32_t kSpinLimit = 1u << 18;
 
+// The flag and the value share one 64-bit word, so a reader never needs any
+// other memory of the writer: relaxed device-scope atomics are enough. (An
+// acquire/release pair would add a write-back or an invalidation of the L2 of
+// the XCD at every publish and every poll.)
 __device__ __forceinline__ void status_store(uint64_t* p, uint64_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ uint64_t status_load(const uint64_t* p) {
-  return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Exclusive prefix of tile t in a device-wide scan over tiles taken in ticket
-// order. Called by all 64 lanes of one wave; returns the same value in every
-// lane. Tiles below t were handed out before t, so every predecessor is
-// running or done and each wait ends; the spin is still bounded, and on
-// exhaustion the error word is set and the partial prefix returned.
+// Exclusive prefix of tile t in a device-wide scan over tiles, tile t being
+// workgroup t of the launch. Called by all 64 lanes of one wave; returns the
+// same value in every lane. A tile waits only on lower-numbered tiles, and
+// workgroups start in increasing order on each XCD, so the lowest unfinished
+// tile is always running and every wait ends. The spin is bounded all the
+// same: on exhaustion err is raised to err_code and the partial prefix returned.
 __device__ __noinline__ uint64_t lookback_excl(uint64_t* status, uint32_t t, uint64_t agg,
-                                               uint32_t* err) {
+                                               uint32_t* err, uint32_t err_code) {
   const int lane = lane_id();
   if (t == 0) {
     if (lane == 0) status_store(status, kFlagIncl | agg);
@@ -309,10 +314,10 @@ __device__ __noinline__ uint64_t lookback_excl(uint64_t* status, uint32_t t, uin
     const uint64_t need = first >= 63 ? ~0ull : ((2ull << first) - 1);
     if (inval & need) {
       if (++spins > kSpinLimit) {
-        if (lane == 0) atomicOr(err, 1u);
+        if (lane == 0) atomicMax(err, err_code);
         break;
       }
-      __builtin_amdgcn_s_sleep(2);
+      __builtin_amdgcn_s_sleep(1);
       continue;
     }
     uint64_t v = lane <= first ? (w & kValueMask) : 0ull;

@@ -30,10 +30,8 @@ __host__ __device__ inline Sections sections(uint64_t nblk, uint64_t n_nc, uint6
 
 // Device-side counters at the start of the workspace (256 bytes reserved).
 struct Counters {
-  uint32_t tick_cls;   // tile tickets of the classification pass
-  uint32_t tick_enc;   // tile tickets of the encoding pass
-  uint32_t tick_dec;   // tile tickets of the decoding pass
-  uint32_t err;        // nonzero: a bounded wait gave up
+  uint32_t err;        // nonzero: a bounded wait of the compression gave up
+  uint32_t reserved[3];
   uint64_t klo, khi;   // totalOrder keys of the smallest / largest finite value
   uint64_t n_nc;       // non-constant blocks (raw included)
   uint64_t mid_total;  // mid-byte section size
@@ -60,8 +58,11 @@ __host__ __device__ inline uint32_t tile_blocks(uint32_t b) {
 }
 
 // Workspace carve-up; every piece 256-byte aligned.
+// Most workgroups of the extrema pass; each leaves its finite range here.
+constexpr uint32_t kMaxRangeParts = 4096;
+
 struct WsLayout {
-  uint64_t counters, stats, rec, cls_status, enc_status, dec_rank, dec_mid, total;
+  uint64_t counters, range_part, stats, rec, cls_status, enc_status, dec_rank, dec_mid, total;
 };
 
 __host__ __device__ inline WsLayout ws_layout(uint64_t nblk, uint32_t w, uint32_t b) {
@@ -69,7 +70,8 @@ __host__ __device__ inline WsLayout ws_layout(uint64_t nblk, uint32_t w, uint32_
   const uint64_t ntile = cdiv(nblk, tile_blocks(b)) + 1;
   const uint64_t ncls = cdiv(nblk, kClsTile) + 1;
   L.counters = 0;
-  L.stats = 256;
+  L.range_part = 256;
+  L.stats = align256(L.range_part + (uint64_t)kMaxRangeParts * 16);
   L.rec = align256(L.stats + nblk * 2 * (uint64_t)w);
   L.cls_status = align256(L.rec + nblk * 4);
   L.enc_status = align256(L.cls_status + ncls * 8);

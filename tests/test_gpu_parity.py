@@ -193,3 +193,55 @@ def test_parity_cfg3a_full(eb):
     from paper_2201_13020_amd import synth
     x = synth.make("cfg3a")
     check_parity(x, eb, "rel", 128, "cfg3a")
+
+
+def test_graph_replays_match_eager():
+    """The C ABI is allocation-free and sync-free, so a compress + decompress
+    pair captures into a HIP graph; every replay must match the eager call,
+    with other eager work and synchronisations between the replays."""
+    from paper_2201_13020_amd import szx
+    x_np = smooth(300_001, 9)
+    other_np = smooth(120_000, 10)
+    x = torch.from_numpy(x_np).cuda()
+    other = torch.from_numpy(other_np).cuda()
+    cap = szx.compress_bound(torch.float32, x.shape, 1e-3, "rel", 128)
+    wsz = szx.workspace_size(torch.float32, x.shape, 1e-3, "rel", 128)
+    out = torch.zeros(cap, dtype=torch.uint8, device="cuda")
+    size = torch.zeros(1, dtype=torch.uint64, device="cuda")
+    ws = torch.empty(wsz, dtype=torch.uint8, device="cuda")
+    y = torch.empty_like(x)
+    st = torch.zeros(1, dtype=torch.uint32, device="cuda")
+    exp = dict(dtype=torch.float32, dims=tuple(x.shape), block=128)
+
+    def pair():
+        szx.compress(x, 1e-3, "rel", 128, out=out, out_size=size, ws=ws)
+        szx.decompress(out, cap, exp, out=y, status=st, ws=ws)
+
+    pair()
+    torch.cuda.synchronize()
+    n = int(size.cpu().view(torch.int64).item())
+    ref_stream = out[:n].cpu().numpy().copy()
+    ref_y = y.cpu().numpy().copy()
+    assert np.array_equal(ref_stream, szref.compress(x_np, 1e-3, "rel", 128))
+
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        pair()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        pair()
+    for rep in range(4):
+        out.zero_()
+        y.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert int(size.cpu().view(torch.int64).item()) == n
+        assert np.array_equal(out[:n].cpu().numpy(), ref_stream), f"replay {rep}"
+        assert same_bits(y.cpu().numpy(), ref_y), f"replay {rep}"
+        assert int(st.cpu().view(torch.int32).item()) == 0
+        # unrelated eager work on the same workspace between replays
+        o2, s2 = szx.compress(other, 1e-2, "rel", 64)
+        torch.cuda.synchronize()
