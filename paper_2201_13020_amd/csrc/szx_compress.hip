@@ -1,17 +1,21 @@
 // szx_compress.hip -- compression kernels of the SZx method for gfx950.
 //
 // Pipeline of one sz_compress call (all on the caller's stream):
-//   k_init      clear counters and the tile status words of the scans
-//   k_stats     per-block totalOrder min/max (Alg. 1 "compute mu_k" needs both)
-//               and, for the relative bound, the global finite range
-//   k_classify  bound e, mid-range mu and constant test per block (Alg. 1),
-//               state bits and mu section, list of non-constant blocks through
-//               a single-pass prefix count
-//   k_encode    per non-constant block: normalise, keep K bits (eq. (4)),
-//               shift (eq. (5)), verify the bound, 2-bit leading-byte codes and
-//               mid bytes; the tile's output offset comes from a single-pass
-//               prefix sum over tiles (Sec. V-B); bytes are packed in LDS and
-//               leave in aligned 16-byte stores
+//   k_init      clear counters, tickets and the tile status words of the scans
+//   k_stats     per-block totalOrder min/max (Alg. 1 needs both for mu_k) and,
+//               per workgroup, the finite value range
+//   k_range     the absolute bound e (for the relative bound: eb times the
+//               global finite range, Sec. III footnote), one workgroup
+//   k_classify  mid-range mu and constant test of every block (Alg. 1), the
+//               state bits and the mu section; a light single-pass prefix count
+//               of non-constant blocks gives each encode tile its first rank
+//   k_encode    per non-constant block: normalise, keep K bits (eq. (4)), shift
+//               (eq. (5)), verify the bound where it is not proved a priori,
+//               2-bit leading-byte codes and mid bytes. Persistent workgroups
+//               take tiles from interleaved ticket counters; each tile's output
+//               offset comes from a single-pass prefix sum over tiles (Sec. V-B),
+//               and while a tile waits for it the next tile's data is loaded.
+//               Bytes are packed in LDS and leave in aligned 16-byte stores.
 //   k_finalize  header, section padding, stream size
 #include <algorithm>
 
@@ -22,8 +26,8 @@ namespace szx {
 
 // ------------------------------------------------------------------ init ---
 
-__global__ __launch_bounds__(256) void k_init(Counters* ctr, uint64_t* st1, uint64_t n1,
-                                              uint64_t* st2, uint64_t n2, uint32_t* status) {
+__global__ __launch_bounds__(256) void k_init(Counters* ctr, uint32_t* tickets, uint64_t* st1, uint64_t n1,
+                                              uint64_t* st2, uint64_t n2) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n1 + n2; i += stride) {
     if (i < n1)
@@ -31,14 +35,16 @@ __global__ __launch_bounds__(256) void k_init(Counters* ctr, uint64_t* st1, uint
     else
       st2[i - n1] = 0;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    ctr->err = 0;
-    ctr->klo = ~0ull;
-    ctr->khi = 0;
-    ctr->n_nc = 0;
-    ctr->mid_total = 0;
-    ctr->e_bits = 0;
-    if (status) *status = 0;
+  if (blockIdx.x == 0) {
+    if (threadIdx.x < kTicketClasses) tickets[threadIdx.x * 64] = 0;
+    if (threadIdx.x == 0) {
+      ctr->err = 0;
+      ctr->klo = ~0ull;
+      ctr->khi = 0;
+      ctr->n_nc = 0;
+      ctr->mid_total = 0;
+      ctr->e_bits = 0;
+    }
   }
 }
 
@@ -167,19 +173,14 @@ __global__ __launch_bounds__(256) void k_stats(const T* __restrict__ x, uint64_t
   }
 }
 
-// -------------------------------------------------------------- classify ---
+// ----------------------------------------------------------------- range ---
 
+// The bound e from the parameters and, for the relative bound, the per-
+// workgroup finite ranges of k_stats. One workgroup.
 template <typename T>
-__global__ __launch_bounds__(256) void k_classify(const typename Traits<T>::U* __restrict__ stats,
-                                                  uint8_t* __restrict__ out, uint32_t* __restrict__ rec,
-                                                  uint64_t* cls_status, Counters* ctr, uint64_t nblk,
-                                                  uint64_t mu_off, int rel, double eb,
-                                                  const uint64_t* __restrict__ part, uint32_t nparts) {
-  using U = typename Traits<T>::U;
-  __shared__ uint32_t s_scan[kWavesPerWG];
-  __shared__ uint64_t s_base;
+__global__ __launch_bounds__(256) void k_range(Counters* ctr, const uint64_t* __restrict__ part,
+                                               uint32_t nparts, int rel, double eb) {
   __shared__ uint64_t s_lo[kWavesPerWG], s_hi[kWavesPerWG];
-  // global finite range from the per-workgroup partials of k_stats
   uint64_t lo = ~0ull, hi = 0;
   if (rel) {
     for (uint32_t i = threadIdx.x; i < nparts; i += kWG) {
@@ -187,69 +188,134 @@ __global__ __launch_bounds__(256) void k_classify(const typename Traits<T>::U* _
       lo = a < lo ? a : lo;
       hi = b > hi ? b : hi;
     }
-    lo = group_min<kWave, uint64_t>(lo);
-    hi = group_max<kWave, uint64_t>(hi);
-    if (lane_id() == 0) {
-      s_lo[threadIdx.x / kWave] = lo;
-      s_hi[threadIdx.x / kWave] = hi;
-    }
-    __syncthreads();
-    lo = s_lo[0];
-    hi = s_hi[0];
+  }
+  lo = group_min<kWave, uint64_t>(lo);
+  hi = group_max<kWave, uint64_t>(hi);
+  if (lane_id() == 0) {
+    s_lo[threadIdx.x / kWave] = lo;
+    s_hi[threadIdx.x / kWave] = hi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
     for (int i = 1; i < kWavesPerWG; ++i) {
       lo = s_lo[i] < lo ? s_lo[i] : lo;
       hi = s_hi[i] > hi ? s_hi[i] : hi;
     }
-  }
-  const T e = bound_from<T>(rel, eb, lo, hi);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    lo = s_lo[0] < lo ? s_lo[0] : lo;
+    hi = s_hi[0] > hi ? s_hi[0] : hi;
+    const T e = bound_from<T>(rel, eb, lo, hi);
     ctr->klo = lo;
     ctr->khi = hi;
     ctr->e_bits = (uint64_t)bits_of(e);
   }
-  const uint32_t ntiles = (uint32_t)cdiv(nblk, kClsTile);
-  T* mus = reinterpret_cast<T*>(out + mu_off);
-  {
-    const uint32_t t = blockIdx.x;
-    const uint64_t k = (uint64_t)t * kClsTile + threadIdx.x;
-    bool nc = false;
-    if (k < nblk) {
-      const U kmin = stats[2 * k], kmax = stats[2 * k + 1];
-      T mu = (T)0;
-      if (kmin < FiniteKeys<T>::LO || kmax > FiniteKeys<T>::HI) {
-        nc = true;  // a non-finite value: the block is stored raw, mu = +0
-      } else {
-        const T mn = from_bits<T>(key_to_bits<U>(kmin));
-        const T mx = from_bits<T>(key_to_bits<U>(kmax));
-        int m0;
-        nc = !classify_block<T>(mn, mx, e, mu, m0);
-      }
-      mus[k] = mu;
-    }
-    // state bits: one 64-bit word per wave, written when it covers a block
-    const uint64_t word = __ballot(nc);
-    const uint64_t first = (uint64_t)t * kClsTile + (threadIdx.x & ~63u);
-    if (lane_id() == 0 && first < nblk)
-      *reinterpret_cast<uint64_t*>(out + 96 + first / 8) = word;
-    uint32_t total;
-    const uint32_t ex = wg_excl_sum<uint32_t>(nc ? 1u : 0u, s_scan, total);
-    if (threadIdx.x < kWave) {
-      const uint64_t p = lookback_excl(cls_status, t, total, &ctr->err, 1u);
-      if (threadIdx.x == 0) s_base = p;
-    }
-    __syncthreads();
-    const uint64_t base = s_base;
-    if (nc) rec[base + ex] = (uint32_t)k;
-    if (t == ntiles - 1 && threadIdx.x == 0) ctr->n_nc = base + total;
+}
+
+// Parameters of one block from its totalOrder extrema (keys): K = -1 for a
+// block with a non-finite value (stored raw), 0 for a constant block, else the
+// kept bits of eq. (4). verify is false where the bound is proved a priori.
+template <typename T>
+struct BlockPlan {
+  T mu;
+  int K;
+  bool verify;
+};
+
+template <typename T>
+__device__ __forceinline__ BlockPlan<T> plan_block(typename Traits<T>::U kmin, typename Traits<T>::U kmax, T e) {
+  using U = typename Traits<T>::U;
+  BlockPlan<T> p;
+  p.mu = (T)0;
+  p.K = -1;
+  p.verify = true;
+  if (kmin < FiniteKeys<T>::LO || kmax > FiniteKeys<T>::HI) return p;
+  const T mn = from_bits<T>(key_to_bits<U>(kmin));
+  const T mx = from_bits<T>(key_to_bits<U>(kmax));
+  int m0;
+  if (classify_block<T>(mn, mx, e, p.mu, m0)) {
+    p.K = 0;
+    return p;
   }
+  p.K = kept_bits<T>(m0);
+  // A priori bound: truncation errs by < 2^p(e); the two roundings (of x - mu
+  // and of mu + v') by at most 2^(p(M) - (mantissa bits - 2)) together, with
+  // M = max(|mn|, |mx|). If e - 2^p(e) covers that, every value passes.
+  constexpr int MANT = Traits<T>::W - 1 - Traits<T>::E;
+  const U emask = FiniteKeys<T>::EXPMASK;
+  const U ebits = bits_of(e);
+  const U pow2_bits = (ebits & emask) ? (ebits & emask) : ((U)1 << MANT);
+  const T slack = e - from_bits<T>(pow2_bits);  // exact: same binade
+  const T amn = mn < (T)0 ? -mn : mn, amx = mx < (T)0 ? -mx : mx;
+  const T M = amn > amx ? amn : amx;
+  const bool slack_normal = slack > (T)0 && (bits_of(slack) & emask) != 0;
+  p.verify = !(slack_normal && exp_of<T>(slack) >= exp_of<T>(M) - (MANT - 2));
+  return p;
+}
+
+// -------------------------------------------------------------- classify ---
+
+// mu and the constant test of every block, the state bits, and the rank of the
+// first non-constant block of every encode tile (a prefix count over tiles of
+// CLS blocks, four per thread at most). The last tile writes n_nc.
+template <typename T, int B>
+__global__ __launch_bounds__(256) void k_classify(const typename Traits<T>::U* __restrict__ stats,
+                                                  uint8_t* __restrict__ out, uint64_t* __restrict__ enc_r0,
+                                                  uint64_t* cls_status, Counters* ctr, uint64_t nblk,
+                                                  uint64_t mu_off) {
+  using U = typename Traits<T>::U;
+  using G = Geo<T, B>;
+  constexpr int TBLK = G::TBLK;
+  constexpr int CLS = TBLK > 1024 ? TBLK : 1024;
+  constexpr int BPT = CLS / kWG;  // blocks per thread
+  __shared__ uint32_t s_scan[kWavesPerWG];
+  __shared__ uint32_t s_state[CLS / 32];
+  __shared__ uint64_t s_base;
+  const T e = from_bits<T>((U)ctr->e_bits);
+  const uint32_t ntiles = (uint32_t)cdiv(nblk, CLS);
+  const uint32_t t = blockIdx.x;
+  T* mus = reinterpret_cast<T*>(out + mu_off);
+  for (int i = threadIdx.x; i < CLS / 32; i += kWG) s_state[i] = 0;
+  __syncthreads();
+  const uint64_t k0 = (uint64_t)t * CLS + (uint64_t)threadIdx.x * BPT;
+  uint32_t cnt = 0, bits = 0;
+#pragma unroll
+  for (int i = 0; i < BPT; ++i) {
+    const uint64_t k = k0 + i;
+    if (k < nblk) {
+      const BlockPlan<T> p = plan_block<T>(stats[2 * k], stats[2 * k + 1], e);
+      mus[k] = p.mu;
+      const bool nc = p.K != 0;
+      cnt += nc ? 1u : 0u;
+      bits |= (nc ? 1u : 0u) << i;
+    }
+  }
+  if (bits) atomicOr(&s_state[(threadIdx.x * BPT) / 32], bits << ((threadIdx.x * BPT) % 32));
+  uint32_t total;
+  const uint32_t ex = wg_excl_sum<uint32_t>(cnt, s_scan, total);  // has barriers
+  if (threadIdx.x < kWave) {
+    if (threadIdx.x == 0) lookback_publish(cls_status, t, total);
+    const uint64_t p = lookback_resolve(cls_status, t, total, &ctr->err, 1u);
+    if (threadIdx.x == 0) s_base = p;
+  }
+  // state bytes of this tile, never past the state section
+  const uint64_t state_bytes = (nblk + 7) / 8;
+  for (int i = threadIdx.x; i < CLS / 8; i += kWG) {
+    const uint64_t byte = (uint64_t)t * (CLS / 8) + i;
+    if (byte < state_bytes) out[96 + byte] = (uint8_t)(s_state[i / 4] >> (8 * (i % 4)));
+  }
+  __syncthreads();
+  const uint64_t base = s_base;
+  // first rank of every encode tile that starts in this thread's blocks
+  if ((k0 % TBLK) == 0 && k0 < nblk) enc_r0[k0 / TBLK] = base + ex;
+  if (t == ntiles - 1 && threadIdx.x == 0) ctr->n_nc = base + total;
 }
 
 // ---------------------------------------------------------------- encode ---
 
 // Truncate v = x - mu to K leading bits, shifted right by s into nb whole
-// bytes, and check that every valid value reconstructs within e exactly.
+// bytes; when verify is set, check that every valid value reconstructs within
+// e exactly. Returns false if some value fails.
 template <typename T, int EPL>
-__device__ __forceinline__ bool encode_try(const T (&x)[EPL], int cnt, T mu, T e, int K,
+__device__ __forceinline__ bool encode_try(const T (&x)[EPL], int cnt, T mu, T e, int K, bool verify,
                                            typename Traits<T>::U (&q)[EPL]) {
   using U = typename Traits<T>::U;
   const int s = shift_of(K);
@@ -259,30 +325,14 @@ __device__ __forceinline__ bool encode_try(const T (&x)[EPL], int cnt, T mu, T e
   for (int i = 0; i < EPL; ++i) {
     const T v = x[i] - mu;
     const U qi = (U)(bits_of(v) >> s) & keep;
-    const T xr = mu + from_bits<T>((U)(qi << s));
-    const bool good = exact_le<T>(x[i], xr, e) && exact_le<T>(xr, x[i], e);
-    ok = ok && (good || i >= cnt);
     q[i] = qi;
+    if (verify) {
+      const T xr = mu + from_bits<T>((U)(qi << s));
+      const bool good = exact_le<T>(x[i], xr, e) && exact_le<T>(xr, x[i], e);
+      ok = ok && (good || i >= cnt);
+    }
   }
   return ok;
-}
-
-// OR a string of L <= sizeof(U) bytes (first byte in the low byte of sv) into
-// the LDS byte stream at byte offset off.
-__device__ __forceinline__ void lds_put(uint32_t* stage, uint32_t off, uint32_t sv) {
-  const uint32_t d = off >> 2, sh = (off & 3u) * 8u;
-  const uint32_t lo = sv << sh;
-  const uint32_t hi = sh ? (sv >> (32u - sh)) : 0u;
-  if (lo) atomicOr(stage + d, lo);
-  if (hi) atomicOr(stage + d + 1, hi);
-}
-__device__ __forceinline__ void lds_put(uint32_t* stage, uint32_t off, uint64_t sv) {
-  const uint32_t d = off >> 2, sh = (off & 3u) * 8u;
-  const uint64_t lo = sv << sh;
-  const uint32_t hi = sh ? (uint32_t)(sv >> (64u - sh)) : 0u;
-  if ((uint32_t)lo) atomicOr(stage + d, (uint32_t)lo);
-  if ((uint32_t)(lo >> 32)) atomicOr(stage + d + 1, (uint32_t)(lo >> 32));
-  if (hi) atomicOr(stage + d + 2, hi);
 }
 
 template <typename U>
@@ -290,7 +340,45 @@ __device__ __forceinline__ U low_bytes_mask(int L) {
   return L >= (int)sizeof(U) ? (U)~(U)0 : (U)(((U)1 << (8 * L)) - 1);
 }
 
-// Copy the staged bytes [0, st + total) to dst_base + [st, st + total), where
+// Appends byte strings to a lane's run of the LDS byte stream. Whole dwords
+// the lane owns are written plainly; the first and last, which it may share
+// with its neighbours, are OR-ed into a zeroed stream.
+struct LanePacker {
+  uint32_t* stage;
+  uint32_t d;     // dword being filled
+  uint64_t acc;   // pending bytes, the next byte of the stream in the low byte
+  uint32_t fill;  // pending bits
+  bool first;
+  __device__ __forceinline__ LanePacker(uint32_t* st, uint32_t off)
+      : stage(st), d(off >> 2), acc(0), fill((off & 3u) * 8u), first(true) {}
+  // L <= 4 bytes of sv, first byte in the low byte
+  __device__ __forceinline__ void put4(uint32_t sv, int L) {
+    acc |= (uint64_t)sv << fill;
+    fill += 8u * (uint32_t)L;
+    if (fill >= 32) {
+      const uint32_t w = (uint32_t)acc;
+      if (first)
+        atomicOr(stage + d, w);
+      else
+        stage[d] = w;
+      first = false;
+      ++d;
+      acc >>= 32;
+      fill -= 32;
+    }
+  }
+  __device__ __forceinline__ void put(uint32_t sv, int L) { put4(sv, L); }
+  __device__ __forceinline__ void put(uint64_t sv, int L) {
+    const int a = L < 4 ? L : 4;
+    put4((uint32_t)sv, a);
+    put4((uint32_t)(sv >> 32), L - a);
+  }
+  __device__ __forceinline__ void flush() {
+    if (fill > 0) atomicOr(stage + d, (uint32_t)acc);
+  }
+};
+
+// Copy the staged bytes [st, st + total) to dst_base + [st, st + total), where
 // dst_base is 16-byte aligned: whole 16-byte chunks as single stores, the
 // shared first and last chunks byte by byte.
 __device__ __forceinline__ void copy_out(uint8_t* __restrict__ dst_base, const uint32_t* stage,
@@ -309,142 +397,208 @@ __device__ __forceinline__ void copy_out(uint8_t* __restrict__ dst_base, const u
   }
 }
 
+// What a workgroup holds of one tile between its loads and its encoding.
+template <typename T, int B>
+struct TileIn {
+  T x[Geo<T, B>::SUB][Geo<T, B>::EPL];
+  T mu[Geo<T, B>::SUB];
+  int K[Geo<T, B>::SUB];  // plan: -1 raw, 0 constant or no block, else kept bits
+  bool verify[Geo<T, B>::SUB];
+  int cnt[Geo<T, B>::SUB];
+  uint32_t rank[Geo<T, B>::SUB];  // rank of the row's block among the tile's non-constant ones
+  uint64_t r0;                    // rank of the tile's first non-constant block
+};
+
+// Loads and plans tile t: extrema, plan, ranks within the tile (barriers),
+// and the values of its non-constant blocks (left in flight).
+template <typename T, int B>
+__device__ __forceinline__ void tile_load(TileIn<T, B>& in, uint32_t t, const T* __restrict__ x,
+                                          const typename Traits<T>::U* __restrict__ stats,
+                                          const uint64_t* __restrict__ enc_r0, uint64_t n, uint64_t nblk,
+                                          T e, uint32_t* s_scan) {
+  using G = Geo<T, B>;
+  constexpr int EPL = G::EPL, LPB = G::LPB, TB = G::TB, SUB = G::SUB, TBLK = G::TBLK;
+  const int g = threadIdx.x / LPB, lig = threadIdx.x % LPB;
+  in.r0 = enc_r0[t];
+  uint32_t first[SUB];
+#pragma unroll
+  for (int s = 0; s < SUB; ++s) {
+    const uint64_t k = (uint64_t)t * TBLK + (uint64_t)s * TB + g;
+    BlockPlan<T> p;
+    p.mu = (T)0;
+    p.K = 0;
+    p.verify = false;
+    if (k < nblk) p = plan_block<T>(stats[2 * k], stats[2 * k + 1], e);
+    in.mu[s] = p.mu;
+    in.K[s] = p.K;
+    in.verify[s] = p.verify;
+    const uint64_t nk = (k < nblk && p.K != 0) ? std::min<uint64_t>((uint64_t)B, n - k * B) : 0;
+    in.cnt[s] = (int)((uint64_t)lig * EPL >= nk ? 0 : std::min<uint64_t>(EPL, nk - (uint64_t)lig * EPL));
+    load_run<T, EPL>(x, k * B + (uint64_t)lig * EPL, k * B + nk, in.x[s]);
+    first[s] = (lig == 0 && p.K != 0) ? 1u : 0u;
+  }
+  uint32_t tot[SUB];
+  wg_excl_scan_multi<SUB>(first, in.rank, tot, s_scan);
+  const int lane = lane_id();
+#pragma unroll
+  for (int s = 0; s < SUB; ++s) in.rank[s] = __shfl(in.rank[s], lane - lig);
+}
+
 template <typename T, int B>
 __global__ __launch_bounds__(256) void k_encode(const T* __restrict__ x, uint8_t* __restrict__ out,
                                                 const typename Traits<T>::U* __restrict__ stats,
-                                                const uint32_t* __restrict__ rec, uint64_t* enc_status,
-                                                Counters* ctr, uint64_t n, uint64_t nblk, uint64_t mu_off) {
+                                                const uint64_t* __restrict__ enc_r0, uint64_t* mid_status,
+                                                uint32_t* tickets, Counters* ctr, uint64_t n, uint64_t nblk,
+                                                uint64_t mu_off) {
   using U = typename Traits<T>::U;
   using G = Geo<T, B>;
-  constexpr int EPL = G::EPL, LPB = G::LPB, TB = G::TB;
+  constexpr int EPL = G::EPL, LPB = G::LPB, SUB = G::SUB;
   constexpr int BYTES = Traits<T>::BYTES;
-  constexpr int STAGE_WORDS = (G::TILE * BYTES + 16) / 4 + 4;
-  __shared__ uint32_t s_scan[kWavesPerWG];
+  constexpr int STAGE_WORDS = (G::TILE * SUB * BYTES + 16) / 4 + 8;
+  __shared__ uint32_t s_scan[SUB * kWavesPerWG];
+  __shared__ uint32_t s_tile;
   __shared__ uint64_t s_base;
   __shared__ __align__(16) uint32_t s_stage[STAGE_WORDS];
 
   const uint64_t n_nc = ctr->n_nc;
   const T e = from_bits<T>((U)ctr->e_bits);
   const Sections sec = sections(nblk, n_nc, BYTES, B, 0);
-  const uint32_t ntiles = (uint32_t)cdiv(n_nc, TB);
+  const uint32_t ntiles = (uint32_t)cdiv(nblk, G::TBLK);
+  const uint32_t cls = blockIdx.x % kTicketClasses;
   T* mus = reinterpret_cast<T*>(out + mu_off);
-  const int g = threadIdx.x / LPB, lig = threadIdx.x % LPB;
+  const int lig = threadIdx.x % LPB;
 
-  {
-    const uint32_t t = blockIdx.x;
-    if (t >= ntiles) return;  // the grid covers every block; fewer are non-constant
+  auto claim = [&]() -> uint32_t {
+    if (threadIdx.x == 0) s_tile = atomicAdd(tickets + cls * 64, 1u) * kTicketClasses + cls;
+    __syncthreads();
+    const uint32_t v = s_tile;
+    __syncthreads();
+    return v;
+  };
 
-    const uint64_t r = (uint64_t)t * TB + g;
-    const bool active = r < n_nc;
-    const uint64_t k = active ? rec[r] : 0;
-    const uint64_t nk = active ? ((n - k * B) < (uint64_t)B ? (n - k * B) : (uint64_t)B) : 0;
-    const int cnt = (int)((uint64_t)lig * EPL >= nk ? 0 : (nk - (uint64_t)lig * EPL > (uint64_t)EPL ? EPL : nk - (uint64_t)lig * EPL));
-    T xv[EPL];
-    load_run<T, EPL>(x, k * B + (uint64_t)lig * EPL, k * B + nk, xv);
+  for (int i = threadIdx.x; i < STAGE_WORDS / 4; i += kWG)
+    reinterpret_cast<uint4*>(s_stage)[i] = make_uint4(0, 0, 0, 0);
+  uint32_t t = claim();
+  if (t >= ntiles) return;
+  TileIn<T, B> cur;
+  tile_load<T, B>(cur, t, x, stats, enc_r0, n, nblk, e, s_scan);
 
-    // block parameters from the extrema
-    int K = -1;  // -1: raw
-    T mu = (T)0;
-    if (active) {
-      const U kmin = stats[2 * k], kmax = stats[2 * k + 1];
-      if (!(kmin < FiniteKeys<T>::LO || kmax > FiniteKeys<T>::HI)) {
-        const T mn = from_bits<T>(key_to_bits<U>(kmin));
-        const T mx = from_bits<T>(key_to_bits<U>(kmax));
-        int m0;
-        classify_block<T>(mn, mx, e, mu, m0);
-        K = kept_bits<T>(m0);
-      }
-    }
-    // error control: K0, then one more bit, then raw (all lanes take part in
-    // the votes; inactive and raw groups vote yes)
-    U q[EPL];
-    bool ok = encode_try<T, EPL>(xv, K > 0 ? cnt : 0, mu, e, K > 0 ? K : Traits<T>::W, q);
-    bool pass = group_all<LPB>(ok);
-    if (K > 0 && !pass) {
-      const int K1 = kept_bits<T>(K - Traits<T>::KMIN + 1);
-      if (K1 != K) {
-        ok = encode_try<T, EPL>(xv, cnt, mu, e, K1, q);
-        K = K1;
-      } else {
-        ok = false;
-      }
-    } else {
-      ok = true;
-    }
-    pass = group_all<LPB>(ok);
-    if (!pass) K = -1;
-
-    // codes and per-value byte counts
-    const bool raw = K < 0;
-    const int nb = raw ? 0 : bytes_of(K);
-    U prev = __shfl_up(q[EPL - 1], 1, LPB);
-    if (lig == 0) prev = 0;
-    uint32_t codes = 0;  // EPL codes, 2 bits each, first value most significant
-    int c[EPL];
-    uint32_t lane_bytes = 0;
+  for (;;) {
+    // encode the current tile: error control K0, then one more mantissa bit,
+    // then raw. Every lane votes; lanes without a coded block vote yes.
+    U q[SUB][EPL];
+    int Ks[SUB];
+    uint32_t cw[SUB], nbytes[SUB];
 #pragma unroll
-    for (int i = 0; i < EPL; ++i) {
-      int ci = same_lead_bytes(q[i], prev);
-      ci = ci > 3 ? 3 : ci;
-      ci = ci > nb ? nb : ci;
-      ci = (raw || i >= cnt) ? 0 : ci;
-      c[i] = ci;
-      codes |= (uint32_t)ci << (2 * (EPL - 1 - i));
-      prev = q[i];
-      lane_bytes += i < cnt ? (raw ? BYTES : nb - ci) : 0;
+    for (int s = 0; s < SUB; ++s) {
+      int K = cur.K[s];
+      const bool coded = K > 0;
+      bool ok = encode_try<T, EPL>(cur.x[s], coded ? cur.cnt[s] : 0, cur.mu[s], e, coded ? K : Traits<T>::W,
+                                   coded && cur.verify[s], q[s]);
+      if (!group_all<LPB>(ok)) {  // only coded blocks can fail
+        const int K1 = kept_bits<T>(K - Traits<T>::KMIN + 1);
+        bool ok1 = false;
+        if (K1 != K) ok1 = encode_try<T, EPL>(cur.x[s], cur.cnt[s], cur.mu[s], e, K1, true, q[s]);
+        K = group_all<LPB>(ok1) ? K1 : -1;
+      }
+      const bool raw = K < 0;
+      if (raw) {
+#pragma unroll
+        for (int i = 0; i < EPL; ++i) q[s][i] = bits_of(cur.x[s][i]);
+      }
+      // 2-bit codes of identical leading bytes and per-value byte counts
+      const int nb = K > 0 ? bytes_of(K) : 0;
+      U prev = __shfl_up(q[s][EPL - 1], 1, LPB);
+      prev = lig == 0 ? (U)0 : prev;
+      uint32_t codes = 0, lb = 0;
+#pragma unroll
+      for (int i = 0; i < EPL; ++i) {
+        int ci = same_lead_bytes(q[s][i], prev);
+        ci = ci > 3 ? 3 : ci;
+        ci = ci > nb ? nb : ci;
+        ci = (K > 0 && i < cur.cnt[s]) ? ci : 0;
+        codes |= (uint32_t)ci << (2 * (EPL - 1 - i));
+        prev = q[s][i];
+        lb += i < cur.cnt[s] ? (raw ? BYTES : nb - ci) : 0;
+      }
+      Ks[s] = K;
+      cw[s] = codes;
+      nbytes[s] = lb;
     }
-    uint32_t tile_bytes;
-    const uint32_t lane_off = wg_excl_sum<uint32_t>(lane_bytes, s_scan, tile_bytes);
+    uint32_t off[SUB], tot[SUB];
+    wg_excl_scan_multi<SUB>(nbytes, off, tot, s_scan);
+    uint32_t tile_bytes = 0;
+#pragma unroll
+    for (int s = 0; s < SUB; ++s) tile_bytes += tot[s];
+    if (threadIdx.x == 0) lookback_publish(mid_status, t, tile_bytes);
+    const uint64_t r0 = cur.r0;
+    uint32_t rank[SUB];
+    bool rawk[SUB];
+    int cnts[SUB];
+#pragma unroll
+    for (int s = 0; s < SUB; ++s) {
+      rank[s] = cur.rank[s];
+      rawk[s] = cur.K[s] > 0 && Ks[s] < 0;
+      cnts[s] = cur.cnt[s];
+    }
+    const uint32_t t_cur = t;
 
-    // zero the staging area while wave 0 resolves the tile's output offset
-    for (int i = threadIdx.x; i < STAGE_WORDS / 4; i += kWG)
-      reinterpret_cast<uint4*>(s_stage)[i] = make_uint4(0, 0, 0, 0);
+    // the next tile's loads go out while this tile's offset is resolved
+    t = claim();
+    const bool more = t < ntiles;
+    if (more) tile_load<T, B>(cur, t, x, stats, enc_r0, n, nblk, e, s_scan);
     if (threadIdx.x < kWave) {
-      const uint64_t p = lookback_excl(enc_status, t, tile_bytes, &ctr->err, 1u);
+      const uint64_t p = lookback_resolve(mid_status, t_cur, tile_bytes, &ctr->err, 1u);
       if (threadIdx.x == 0) s_base = p;
+    }
+    // K bytes, codes and the mu of escalated raw blocks
+#pragma unroll
+    for (int s = 0; s < SUB; ++s) {
+      if (Ks[s] != 0) {
+        const uint64_t r = r0 + rank[s];
+        const uint64_t k = (uint64_t)t_cur * G::TBLK + (uint64_t)s * G::TB + threadIdx.x / LPB;
+        if (lig == 0) {
+          out[sec.kbytes + r] = Ks[s] < 0 ? kRawK : (uint8_t)Ks[s];
+          if (rawk[s]) mus[k] = (T)0;
+        }
+        uint8_t* cdst = out + sec.codes + r * (B / 4) + (uint64_t)lig * (EPL / 4);
+        if constexpr (EPL == 8) {
+          const uint16_t wv = (uint16_t)(((cw[s] >> 8) & 0xFFu) | ((cw[s] & 0xFFu) << 8));
+          *reinterpret_cast<uint16_t*>(cdst) = wv;
+        } else {
+#pragma unroll
+          for (int j = 0; j < EPL / 4; ++j) cdst[j] = (uint8_t)(cw[s] >> (8 * (EPL / 4 - 1 - j)));
+        }
+      }
     }
     __syncthreads();
     const uint64_t base = s_base;
     const uint64_t gdst = sec.mid + base;
     const uint32_t st = (uint32_t)(gdst & 15u);
-
-    if (active) {
-      if (lig == 0) {
-        out[sec.kbytes + r] = raw ? kRawK : (uint8_t)K;
-        if (raw) mus[k] = (T)0;
-      }
-      // this lane's codes: EPL/4 bytes, first value in the top bits of the first byte
-      uint8_t* cdst = out + sec.codes + r * (B / 4) + (uint64_t)lig * (EPL / 4);
-      if constexpr (EPL == 8) {
-        const uint16_t wv = (uint16_t)(((codes >> 8) & 0xFFu) | ((codes & 0xFFu) << 8));
-        *reinterpret_cast<uint16_t*>(cdst) = wv;
-      } else {
-#pragma unroll
-        for (int j = 0; j < EPL / 4; ++j) cdst[j] = (uint8_t)(codes >> (8 * (EPL / 4 - 1 - j)));
-      }
-    }
     // stage the kept bytes of each value, most significant first
-    uint32_t off = st + lane_off;
 #pragma unroll
-    for (int i = 0; i < EPL; ++i) {
-      if (i < cnt) {
-        if (raw) {
-          lds_put(s_stage, off, (U)bits_of(xv[i]));
-          off += BYTES;
-        } else {
-          const int L = nb - c[i];
-          if (L > 0) {
-            const U img = byte_swap(q[i]);
-            const U sv = (U)(img >> (8 * c[i])) & low_bytes_mask<U>(L);
-            lds_put(s_stage, off, sv);
-          }
-          off += L;
-        }
+    for (int s = 0; s < SUB; ++s) {
+      const int K = Ks[s];
+      const bool raw = K < 0;
+      const int nb = raw ? BYTES : (K > 0 ? bytes_of(K) : 0);
+      LanePacker pk(s_stage, st + off[s]);
+#pragma unroll
+      for (int i = 0; i < EPL; ++i) {
+        const int ci = raw ? 0 : (int)((cw[s] >> (2 * (EPL - 1 - i))) & 3u);
+        const int Li = (K != 0 && i < cnts[s]) ? nb - ci : 0;
+        const U img = raw ? q[s][i] : byte_swap(q[s][i]);
+        const U sv = Li > 0 ? (U)((img >> (8 * ci)) & low_bytes_mask<U>(Li)) : (U)0;
+        pk.put(sv, Li);
       }
+      pk.flush();
     }
     __syncthreads();
     copy_out(out + (gdst - st), s_stage, st, tile_bytes);
-    if (t == ntiles - 1 && threadIdx.x == 0) ctr->mid_total = base + tile_bytes;
+    if (t_cur == ntiles - 1 && threadIdx.x == 0) ctr->mid_total = base + tile_bytes;
+    __syncthreads();
+    for (int i = threadIdx.x; i < STAGE_WORDS / 4; i += kWG)
+      reinterpret_cast<uint4*>(s_stage)[i] = make_uint4(0, 0, 0, 0);
+    if (!more) break;
   }
 }
 
@@ -479,7 +633,7 @@ __global__ void k_finalize(uint8_t* __restrict__ out, uint64_t* out_size, const 
     *out_size = ctr->err ? 0 : s.total;
   }
   // zero padding: after the state words, after mu, after K, after codes
-  const uint64_t pads[4][2] = {{96 + 8 * cdiv(h.nblk, 64), s.mu},
+  const uint64_t pads[4][2] = {{96 + cdiv(h.nblk, 8), s.mu},
                                {s.mu + h.nblk * h.w, s.kbytes},
                                {s.kbytes + n_nc, s.codes},
                                {s.codes + n_nc * (h.b / 4), s.mid}};
@@ -493,15 +647,17 @@ template <typename T, int B>
 hipError_t launch_compress_t(const Job& j, const CompressLaunch& L, TimerHook hook) {
   using U = typename Traits<T>::U;
   using G = Geo<T, B>;
+  constexpr uint32_t CLS = G::TBLK > 1024 ? G::TBLK : 1024;
   const WsLayout W = ws_layout(j.nblk, j.w, j.b);
   Counters* ctr = reinterpret_cast<Counters*>(L.ws + W.counters);
+  uint32_t* tickets = reinterpret_cast<uint32_t*>(L.ws + W.tickets);
   U* stats = reinterpret_cast<U*>(L.ws + W.stats);
-  uint32_t* rec = reinterpret_cast<uint32_t*>(L.ws + W.rec);
-  uint64_t* cls_st = reinterpret_cast<uint64_t*>(L.ws + W.cls_status);
-  uint64_t* enc_st = reinterpret_cast<uint64_t*>(L.ws + W.enc_status);
   uint64_t* part = reinterpret_cast<uint64_t*>(L.ws + W.range_part);
-  const uint64_t ncls = cdiv(j.nblk, kClsTile) + 1;
-  const uint64_t nenc = cdiv(j.nblk, G::TB) + 1;
+  uint64_t* enc_r0 = reinterpret_cast<uint64_t*>(L.ws + W.enc_r0);
+  uint64_t* cls_st = reinterpret_cast<uint64_t*>(L.ws + W.cls_status);
+  uint64_t* enc_mid = reinterpret_cast<uint64_t*>(L.ws + W.enc_mid);
+  const uint64_t ncls = cdiv(j.nblk, CLS);
+  const uint64_t nenc = cdiv(j.nblk, G::TBLK);
   const Sections sec0 = sections(j.nblk, 0, j.w, j.b, 0);
 
   auto run = [&](const char* name, auto&& fn) {
@@ -510,8 +666,8 @@ hipError_t launch_compress_t(const Job& j, const CompressLaunch& L, TimerHook ho
     if (hook) hook(name, L.stream, 0);
   };
   {
-    const uint32_t grid = (uint32_t)std::min<uint64_t>(cdiv(ncls + nenc, 256), 1024);
-    run("k_init", [&] { k_init<<<grid, 256, 0, L.stream>>>(ctr, cls_st, ncls, enc_st, nenc, nullptr); });
+    const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(cdiv(ncls + nenc, 256), 1024));
+    run("k_init", [&] { k_init<<<grid, 256, 0, L.stream>>>(ctr, tickets, cls_st, ncls, enc_mid, nenc); });
   }
   if (j.nblk > 0) {
     const uint64_t ntile = cdiv(j.n, (uint64_t)G::TILE);
@@ -519,15 +675,17 @@ hipError_t launch_compress_t(const Job& j, const CompressLaunch& L, TimerHook ho
     run("k_stats", [&] {
       k_stats<T, B><<<grid, 256, 0, L.stream>>>((const T*)L.in, j.n, j.nblk, stats, part);
     });
-    const uint32_t gcls = (uint32_t)cdiv(j.nblk, kClsTile);
-    run("k_classify", [&] {
-      k_classify<T><<<gcls, 256, 0, L.stream>>>(stats, L.out, rec, cls_st, ctr, j.nblk, sec0.mu,
-                                                j.eb_mode == 1 ? 1 : 0, j.eb, part, grid);
+    run("k_range", [&] {
+      k_range<T><<<1, 256, 0, L.stream>>>(ctr, part, grid, j.eb_mode == 1 ? 1 : 0, j.eb);
     });
-    const uint32_t genc = (uint32_t)cdiv(j.nblk, G::TB);
+    run("k_classify", [&] {
+      k_classify<T, B><<<(uint32_t)ncls, 256, 0, L.stream>>>(stats, L.out, enc_r0, cls_st, ctr, j.nblk, sec0.mu);
+    });
+    // persistent: a few workgroups per CU, at least one per ticket class
+    const uint32_t genc = (uint32_t)std::min<uint64_t>(nenc, (uint64_t)L.n_cu * 4);
     run("k_encode", [&] {
-      k_encode<T, B><<<genc, 256, 0, L.stream>>>((const T*)L.in, L.out, stats, rec, enc_st, ctr, j.n,
-                                                  j.nblk, sec0.mu);
+      k_encode<T, B><<<genc, 256, 0, L.stream>>>((const T*)L.in, L.out, stats, enc_r0, enc_mid, tickets, ctr,
+                                                  j.n, j.nblk, sec0.mu);
     });
   }
   HeaderArgs h;

@@ -1,23 +1,23 @@
-// szx_decompress.hip -- decompression kernel of the SZx method for gfx950.
+// szx_decompress.hip -- decompression kernels of the SZx method for gfx950.
 //
-// One persistent kernel over tiles of consecutive blocks, tiles taken in
-// workgroup order (tile t = workgroup t). Per tile:
-//   1. state bits -> the tile's non-constant blocks; a device-wide prefix count
-//      (decoupled look-back) gives their ranks, hence their K byte and codes;
-//   2. per value, the count of stored mid bytes (kept bytes minus the leading
-//      bytes the 2-bit code says are shared); a second device-wide prefix sum
-//      gives the tile's first mid byte ("a parallel prefix-scan is applied
-//      before retrieving the mid-bytes", Sec. V-B);
-//   3. the tile's mid bytes are staged in LDS with aligned 16-byte loads;
-//   4. leading bytes: byte j of value i is the stored byte j of the nearest
-//      value i' <= i whose code stores byte j (Sec. V-B, index propagation).
-//      This is one inclusive scan over (code, top bytes) pairs with the
-//      associative operator (c_a, S_a) . (c_b, S_b) = (min(c_a, c_b),
-//      (S_a & top(c_b)) | S_b);
-//   5. x' = mu + (q' << s); constant blocks are filled with mu, raw blocks
-//      copied.
+// Two kernels per call:
+//   k_dindex  over tiles of consecutive blocks: state bits give each tile's
+//             non-constant blocks, a light single-pass prefix count their
+//             ranks (hence their K byte and codes); per value the number of
+//             stored mid bytes is the kept bytes minus the leading bytes its
+//             2-bit code shares, and a second light prefix sum gives the first
+//             mid byte of every decode tile ("a parallel prefix-scan is applied
+//             before retrieving the mid-bytes", Sec. V-B).
+//   k_decode  every decode tile on its own, no waiting: it stages its mid bytes
+//             in LDS with aligned 16-byte loads, resolves leading bytes -- byte
+//             j of value i is the stored byte j of the nearest value i' <= i
+//             whose code stores byte j (Sec. V-B, index propagation) -- with one
+//             inclusive scan over (code, top bytes) pairs under the associative
+//             operator (c_a, S_a) . (c_b, S_b) = (min(c_a, c_b),
+//             (S_a & top(c_b)) | S_b), and writes x' = mu + (q' << s);
+//             constant blocks get mu, raw blocks their stored bytes.
 // Every read of the stream is bounded by in_bytes; a malformed stream sets
-// *status = SZ_ECORRUPT and leaves no buffer.
+// *status = SZ_ECORRUPT and no access leaves the given buffers.
 #include <algorithm>
 
 #include "szx_device.hpp"
@@ -33,7 +33,7 @@ struct DecodeArgs {
   uint64_t in_bytes;
   uint8_t* out;
   uint32_t* status;
-  Counters* ctr;
+  uint64_t* index;  // per decode tile: first rank, first mid byte
   uint64_t* rank_st;
   uint64_t* mid_st;
   uint64_t n, nblk;
@@ -41,12 +41,10 @@ struct DecodeArgs {
   uint64_t dims[4];
 };
 
-__global__ __launch_bounds__(256) void k_dinit(Counters* ctr, uint64_t* st1, uint64_t n1, uint32_t* status) {
+__global__ __launch_bounds__(256) void k_dinit(uint64_t* st1, uint64_t n1, uint32_t* status) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n1; i += stride) st1[i] = 0;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    *status = 0;
-  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *status = 0;
 }
 
 __device__ __forceinline__ uint64_t rd64(const uint8_t* p) { return *reinterpret_cast<const uint64_t*>(p); }
@@ -133,163 +131,294 @@ __device__ __forceinline__ void store_run(T* __restrict__ y, uint64_t i0, int cn
   }
 }
 
+// Header of the stream, checked against the caller's expectations; identical
+// in every workgroup.
+struct StreamInfo {
+  bool ok;
+  uint64_t n_nc, mid_total;
+  Sections sec;
+};
+
+template <int BYTES, int B>
+__device__ __forceinline__ StreamInfo read_header(const DecodeArgs& a) {
+  StreamInfo h;
+  const uint8_t* in = a.in;
+  h.ok = a.in_bytes >= kHeaderBytes;
+  h.n_nc = 0;
+  h.mid_total = 0;
+  h.sec = sections(a.nblk, 0, BYTES, B, 0);
+  if (h.ok) {
+    const uint32_t w1 = rd32(in + 4);
+    h.ok = rd32(in) == kMagic && (w1 & 0xFFu) == kVersion && ((w1 >> 8) & 0xFFu) == a.dtype &&
+           ((w1 >> 16) & 0xFFu) <= 1 && ((w1 >> 24) & 0xFFu) == a.ndims && rd32(in + 8) == (uint32_t)B &&
+           rd64(in + 48) == a.n && rd64(in + 72) == a.nblk;
+    for (int d = 0; d < 4; ++d) h.ok = h.ok && rd64(in + 16 + 8 * d) == a.dims[d];
+    h.n_nc = rd64(in + 80);
+    h.mid_total = rd64(in + 88);
+    h.ok = h.ok && h.n_nc <= a.nblk && h.mid_total <= a.n * BYTES;
+    if (h.ok) {
+      h.sec = sections(a.nblk, h.n_nc, BYTES, B, h.mid_total);
+      h.ok = h.sec.total <= a.in_bytes;
+    }
+  }
+  return h;
+}
+
+// Mid bytes of one non-constant block of nk values with K byte Kb and its
+// codes at cp; raises bad for a K outside [1 + E, W] or a code above the kept
+// bytes.
+template <typename T, int B>
+__device__ __forceinline__ uint32_t block_mid_bytes(const uint8_t* cp, uint32_t Kb, uint32_t nk, bool& bad) {
+  constexpr int BYTES = Traits<T>::BYTES;
+  if (Kb == kRawK) return nk * BYTES;
+  if ((int)Kb < Traits<T>::KMIN || (int)Kb > Traits<T>::W) {
+    bad = true;
+    return 0;
+  }
+  const uint32_t nb = (uint32_t)bytes_of((int)Kb);
+  uint32_t sum = 0, over = 0;
+  // B/4 code bytes, 4 codes per byte, first value in the top bits
+  for (uint32_t j = 0; j < (uint32_t)B / 4; j += 4) {
+    // the block's own code bytes only (b = 8 has two)
+    uint32_t w = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < 4; ++q) w |= (j + q < (uint32_t)B / 4 ? (uint32_t)cp[j + q] : 0u) << (24 - 8 * q);
+    const uint32_t first = 4 * j;  // value index of the top code of w
+    if (first >= nk) break;
+    if (nk - first < 16) w &= ~0u << (2 * (16 - (nk - first)));  // codes past the block end
+    sum += __popc(w & 0x55555555u) + 2u * __popc(w & 0xAAAAAAAAu);
+    over |= w & (w >> 1) & 0x55555555u;  // a code of 3
+  }
+  if (nb == 2 && over) bad = true;
+  return nk * nb - sum;
+}
+
+// Per tile of CLS blocks (four per thread): ranks of the non-constant blocks
+// and mid bytes, each through a light single-pass prefix sum; writes the first
+// rank and first mid byte of every decode tile in it.
+template <typename T, int B>
+__global__ __launch_bounds__(256) void k_dindex(DecodeArgs a) {
+  using G = Geo<T, B>;
+  constexpr int BYTES = Traits<T>::BYTES;
+  constexpr int TBLK = G::TBLK;
+  constexpr int CLS = TBLK > 1024 ? TBLK : 1024;
+  constexpr int BPT = CLS / kWG;
+  __shared__ uint32_t s_scan[kWavesPerWG];
+  __shared__ uint64_t s_r0, s_m0;
+  const StreamInfo h = read_header<BYTES, B>(a);
+  if (!h.ok) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicMax(a.status, kStatusCorrupt);
+    return;
+  }
+  const uint32_t ntiles = (uint32_t)cdiv(a.nblk, CLS);
+  const uint32_t t = blockIdx.x;
+  const uint8_t* in = a.in;
+  const uint64_t k0 = (uint64_t)t * CLS + (uint64_t)threadIdx.x * BPT;
+  bool bad = false;
+  uint32_t ncb = 0, cnt = 0;
+#pragma unroll
+  for (int i = 0; i < BPT; ++i) {
+    const uint64_t k = k0 + i;
+    const bool nc = k < a.nblk && ((in[h.sec.state + (k >> 3)] >> (k & 7)) & 1u);
+    ncb |= (nc ? 1u : 0u) << i;
+    cnt += nc ? 1u : 0u;
+  }
+  uint32_t tnc;
+  const uint32_t rex = wg_excl_sum<uint32_t>(cnt, s_scan, tnc);
+  if (threadIdx.x < kWave) {
+    if (threadIdx.x == 0) lookback_publish(a.rank_st, t, tnc);
+    const uint64_t p = lookback_resolve(a.rank_st, t, tnc, a.status, kStatusDevice);
+    if (threadIdx.x == 0) s_r0 = p;
+  }
+  __syncthreads();
+  const uint64_t R0 = s_r0;
+  uint32_t mid = 0;
+  uint64_t r = R0 + rex;
+#pragma unroll
+  for (int i = 0; i < BPT; ++i) {
+    const uint64_t k = k0 + i;
+    if ((ncb >> i) & 1u) {
+      if (r < h.n_nc) {
+        const uint32_t nk = (uint32_t)std::min<uint64_t>((uint64_t)B, a.n - k * B);
+        mid += block_mid_bytes<T, B>(in + h.sec.codes + r * (B / 4), in[h.sec.kbytes + r], nk, bad);
+      } else {
+        bad = true;
+      }
+      ++r;
+    }
+  }
+  uint32_t tmid;
+  const uint32_t mex = wg_excl_sum<uint32_t>(mid, s_scan, tmid);
+  if (threadIdx.x < kWave) {
+    if (threadIdx.x == 0) lookback_publish(a.mid_st, t, tmid);
+    const uint64_t p = lookback_resolve(a.mid_st, t, tmid, a.status, kStatusDevice);
+    if (threadIdx.x == 0) s_m0 = p;
+  }
+  __syncthreads();
+  const uint64_t M0 = s_m0;
+  if ((k0 % TBLK) == 0 && k0 < a.nblk) {
+    a.index[2 * (k0 / TBLK)] = R0 + rex;
+    a.index[2 * (k0 / TBLK) + 1] = M0 + mex;
+  }
+  if (t == ntiles - 1 && threadIdx.x == 0) {
+    if (R0 + tnc != h.n_nc || M0 + tmid != h.mid_total) bad = true;
+    // the end of the last decode tile
+    a.index[2 * cdiv(a.nblk, TBLK)] = h.n_nc;
+    a.index[2 * cdiv(a.nblk, TBLK) + 1] = h.mid_total;
+  }
+  if (__ballot(bad) != 0 && lane_id() == 0) atomicMax(a.status, kStatusCorrupt);
+}
+
 template <typename T, int B>
 __global__ __launch_bounds__(256) void k_decode(DecodeArgs a) {
   using U = typename Traits<T>::U;
   using G = Geo<T, B>;
-  constexpr int EPL = G::EPL, LPB = G::LPB, TB = G::TB;
+  constexpr int EPL = G::EPL, LPB = G::LPB, TB = G::TB, SUB = G::SUB, TBLK = G::TBLK;
   constexpr int BYTES = Traits<T>::BYTES;
-  constexpr int STAGE_WORDS = (G::TILE * BYTES + 32) / 4 + 4;
-  __shared__ uint32_t s_scan[kWavesPerWG];
-  __shared__ uint64_t s_r0, s_m0;
+  constexpr int STAGE_WORDS = (G::TILE * SUB * BYTES + 32) / 4 + 8;
+  __shared__ uint32_t s_scan[SUB * kWavesPerWG];
   __shared__ __align__(16) uint32_t s_stage[STAGE_WORDS];
 
-  // header checks, identical in every workgroup
+  const StreamInfo h = read_header<BYTES, B>(a);
+  if (!h.ok) return;  // k_dindex reported it
+  const uint32_t ntiles = (uint32_t)cdiv(a.nblk, TBLK);
+  const uint32_t t = blockIdx.x;
+  if (t >= ntiles) return;
   const uint8_t* in = a.in;
-  bool hdr_ok = a.in_bytes >= kHeaderBytes;
-  uint64_t n_nc = 0, mid_total = 0;
-  Sections sec = sections(a.nblk, 0, BYTES, B, 0);
-  if (hdr_ok) {
-    const uint32_t w1 = rd32(in + 4);
-    hdr_ok = rd32(in) == kMagic && (w1 & 0xFFu) == kVersion && ((w1 >> 8) & 0xFFu) == a.dtype &&
-             ((w1 >> 16) & 0xFFu) <= 1 && ((w1 >> 24) & 0xFFu) == a.ndims && rd32(in + 8) == (uint32_t)B &&
-             rd64(in + 48) == a.n && rd64(in + 72) == a.nblk;
-    for (int d = 0; d < 4; ++d) hdr_ok = hdr_ok && rd64(in + 16 + 8 * d) == a.dims[d];
-    n_nc = rd64(in + 80);
-    mid_total = rd64(in + 88);
-    hdr_ok = hdr_ok && n_nc <= a.nblk && mid_total <= a.n * BYTES;
-    if (hdr_ok) {
-      sec = sections(a.nblk, n_nc, BYTES, B, mid_total);
-      hdr_ok = sec.total <= a.in_bytes;
-    }
-  }
-  if (!hdr_ok) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) atomicMax(a.status, kStatusCorrupt);
-    return;
-  }
-
-  const uint32_t ntiles = (uint32_t)cdiv(a.nblk, TB);
   const int g = threadIdx.x / LPB, lig = threadIdx.x % LPB;
   const int lane = lane_id();
-  const T* mus = reinterpret_cast<const T*>(in + sec.mu);
+  const T* mus = reinterpret_cast<const T*>(in + h.sec.mu);
   T* y = reinterpret_cast<T*>(a.out);
+  bool bad = false;
 
+  // the tile's mid bytes: [m0, m1) of the mid section, staged as soon as known
+  const uint64_t r0 = a.index[2 * t];
+  const uint64_t m0 = a.index[2 * t + 1];
+  uint64_t m1 = a.index[2 * t + 3];
+  if (m1 < m0 || m1 - m0 > (uint64_t)G::TILE * SUB * BYTES) {
+    bad = true;
+    m1 = m0;
+  }
+  const uint32_t tile_bytes = (uint32_t)(m1 - m0);
+  const uint64_t src = h.sec.mid + m0;
+  const uint32_t st = (uint32_t)(src & 15u);
   {
-    const uint32_t t = blockIdx.x;
-    if (t >= ntiles) return;
-    bool bad = false;
-
-    const uint64_t k = (uint64_t)t * TB + g;
-    const bool inb = k < a.nblk;
-    const bool nc = inb && ((in[sec.state + (k >> 3)] >> (k & 7)) & 1u);
-    const uint64_t nk = inb ? std::min<uint64_t>((uint64_t)B, a.n - k * B) : 0;
-    const int cnt = (int)((uint64_t)lig * EPL >= nk ? 0 : std::min<uint64_t>(EPL, nk - (uint64_t)lig * EPL));
-
-    // 1. ranks of the tile's non-constant blocks
-    uint32_t tile_nc;
-    const uint32_t rank_in_tile = wg_excl_sum<uint32_t>((lig == 0 && nc) ? 1u : 0u, s_scan, tile_nc);
-    const uint32_t grp_rank = __shfl(rank_in_tile, lane - lig);
-    if (threadIdx.x < kWave) {
-      const uint64_t p = lookback_excl(a.rank_st, t, tile_nc, a.status, kStatusDevice);
-      if (threadIdx.x == 0) s_r0 = p;
+    const uint64_t src0 = src - st;
+    const uint32_t nchunk = (st + tile_bytes + 15) / 16;
+    for (uint32_t ch = threadIdx.x; ch < nchunk; ch += kWG) {
+      const uint64_t gpos = src0 + (uint64_t)ch * 16;
+      uint4 u = make_uint4(0, 0, 0, 0);
+      if (gpos + 16 <= a.in_bytes) {
+        u = *reinterpret_cast<const uint4*>(in + gpos);
+      } else {
+        uint32_t wv[4] = {0, 0, 0, 0};
+        for (int bq = 0; bq < 16; ++bq)
+          if (gpos + bq < a.in_bytes) wv[bq >> 2] |= (uint32_t)in[gpos + bq] << ((bq & 3) * 8);
+        u = make_uint4(wv[0], wv[1], wv[2], wv[3]);
+      }
+      reinterpret_cast<uint4*>(s_stage)[ch] = u;
     }
-    __syncthreads();
-    const uint64_t r = s_r0 + grp_rank;
-    if (t == ntiles - 1 && threadIdx.x == 0 && s_r0 + tile_nc != n_nc) bad = true;
-    const bool have = nc && r < n_nc;
-    bad = bad || (nc && r >= n_nc);
+  }
 
-    // 2. per-value byte counts
-    int K = have ? (int)in[sec.kbytes + r] : 0;
-    const bool raw = have && K == kRawK;
-    if (have && !raw && (K < Traits<T>::KMIN || K > Traits<T>::W)) {
+  // ranks of the tile's non-constant blocks, their K bytes and codes
+  bool nc[SUB];
+  int cnt[SUB];
+  uint32_t first_of[SUB];
+  T mu[SUB];
+#pragma unroll
+  for (int s = 0; s < SUB; ++s) {
+    const uint64_t k = (uint64_t)t * TBLK + (uint64_t)s * TB + g;
+    const bool inb = k < a.nblk;
+    nc[s] = inb && ((in[h.sec.state + (k >> 3)] >> (k & 7)) & 1u);
+    mu[s] = inb ? mus[k] : (T)0;
+    const uint64_t nk = inb ? std::min<uint64_t>((uint64_t)B, a.n - k * B) : 0;
+    cnt[s] = (int)((uint64_t)lig * EPL >= nk ? 0 : std::min<uint64_t>(EPL, nk - (uint64_t)lig * EPL));
+    first_of[s] = (lig == 0 && nc[s]) ? 1u : 0u;
+  }
+  uint32_t rk[SUB], rtot[SUB];
+  wg_excl_scan_multi<SUB>(first_of, rk, rtot, s_scan);
+  int Ks[SUB];       // kept bits; -1 raw; 0 constant or unusable
+  uint32_t cw[SUB];  // this lane's EPL codes, first value in the top bits
+  uint32_t nbytes[SUB];
+#pragma unroll
+  for (int s = 0; s < SUB; ++s) {
+    const uint64_t r = r0 + __shfl(rk[s], lane - lig);
+    const bool have = nc[s] && r < h.n_nc;
+    bad = bad || (nc[s] && r >= h.n_nc);
+    int K = have ? (int)in[h.sec.kbytes + r] : 0;
+    if (K == kRawK) {
+      K = -1;
+    } else if (have && (K < Traits<T>::KMIN || K > Traits<T>::W)) {
       bad = true;
       K = 0;
     }
-    const bool coded = have && !raw && K != 0;
-    const int nb = coded ? bytes_of(K) : 0;
-    uint32_t cw = 0;  // this lane's EPL codes, first value in the top bits
-    if (coded) {
-      const uint8_t* cp = in + sec.codes + r * (B / 4) + (uint64_t)lig * (EPL / 4);
+    const int nb = K > 0 ? bytes_of(K) : 0;
+    uint32_t c = 0;
+    if (K > 0) {
+      const uint8_t* cp = in + h.sec.codes + r * (B / 4) + (uint64_t)lig * (EPL / 4);
+      if constexpr (EPL == 8) {
+        const uint32_t v16 = *reinterpret_cast<const uint16_t*>(cp);
+        c = ((v16 & 0xFFu) << 8) | (v16 >> 8);
+      } else {
 #pragma unroll
-      for (int j = 0; j < EPL / 4; ++j) cw = (cw << 8) | cp[j];
+        for (int j = 0; j < EPL / 4; ++j) c = (c << 8) | cp[j];
+      }
     }
-    int c[EPL];
-    uint32_t lane_bytes = 0;
+    uint32_t lb = 0;
 #pragma unroll
     for (int i = 0; i < EPL; ++i) {
-      int ci = (int)((cw >> (2 * (EPL - 1 - i))) & 3u);
-      if (ci > nb) {
-        bad = bad || (coded && i < cnt);
-        ci = nb;
-      }
-      c[i] = ci;
-      lane_bytes += i < cnt ? (raw ? BYTES : (coded ? nb - ci : 0)) : 0;
+      const int ci = (int)((c >> (2 * (EPL - 1 - i))) & 3u);
+      const bool live = i < cnt[s];
+      bad = bad || (K > 0 && live && ci > nb);
+      const int L = K < 0 ? BYTES : (ci > nb ? 0 : nb - ci);
+      lb += (live && K != 0) ? (uint32_t)L : 0u;
     }
-    uint32_t tile_bytes;
-    const uint32_t lane_off = wg_excl_sum<uint32_t>(lane_bytes, s_scan, tile_bytes);
-    if (threadIdx.x < kWave) {
-      const uint64_t p = lookback_excl(a.mid_st, t, tile_bytes, a.status, kStatusDevice);
-      if (threadIdx.x == 0) s_m0 = p;
-    }
-    __syncthreads();
-    const uint64_t m0 = s_m0;
-    if (m0 + tile_bytes > mid_total) bad = true;
-    if (t == ntiles - 1 && threadIdx.x == 0 && m0 + tile_bytes != mid_total) bad = true;
-
-    // 3. stage the tile's mid bytes, aligned as in the stream
-    const uint64_t src = sec.mid + m0;
-    const uint32_t st = (uint32_t)(src & 15u);
-    const uint64_t src0 = src - st;
-    {
-      const uint32_t nchunk = (st + tile_bytes + 15) / 16;
-      for (uint32_t ch = threadIdx.x; ch < nchunk; ch += kWG) {
-        const uint64_t gpos = src0 + (uint64_t)ch * 16;
-        uint4 u = make_uint4(0, 0, 0, 0);
-        if (gpos + 16 <= a.in_bytes) {
-          u = *reinterpret_cast<const uint4*>(in + gpos);
-        } else {
-          uint32_t wv[4] = {0, 0, 0, 0};
-          for (int bq = 0; bq < 16; ++bq)
-            if (gpos + bq < a.in_bytes) wv[bq >> 2] |= (uint32_t)in[gpos + bq] << ((bq & 3) * 8);
-          u = make_uint4(wv[0], wv[1], wv[2], wv[3]);
-        }
-        reinterpret_cast<uint4*>(s_stage)[ch] = u;
-      }
-    }
-    __syncthreads();
-
-    // 4. values
-    const T mu = inb ? mus[k] : (T)0;
-    T v[EPL];
-    if (!nc || !have) {
+    Ks[s] = K;
+    cw[s] = c;
+    nbytes[s] = lb;
+  }
+  uint32_t off[SUB], tot[SUB];
+  wg_excl_scan_multi<SUB>(nbytes, off, tot, s_scan);  // its barriers also cover the staging
+  uint32_t sum = 0;
 #pragma unroll
-      for (int i = 0; i < EPL; ++i) v[i] = mu;
-    } else if (raw) {
-      uint32_t off = st + lane_off;
+  for (int s = 0; s < SUB; ++s) sum += tot[s];
+  if (sum != tile_bytes) bad = true;
+
+  // values, row by row
+#pragma unroll
+  for (int s = 0; s < SUB; ++s) {
+    const int K = Ks[s];
+    T v[EPL];
+    uint32_t o = st + off[s];
+    if (K <= 0) {
+      // constant (mu) or raw (stored bytes); o only advances for raw blocks
 #pragma unroll
       for (int i = 0; i < EPL; ++i) {
-        v[i] = from_bits<T>(lds_get<U>(s_stage, off));
-        off += i < cnt ? BYTES : 0;
+        const U raw = lds_get<U>(s_stage, o < STAGE_WORDS * 4 - 12 ? o : 0);
+        v[i] = K < 0 ? from_bits<T>(raw) : mu[s];
+        o += (K < 0 && i < cnt[s]) ? BYTES : 0;
       }
     } else {
-      const int s = shift_of(K > 0 ? K : Traits<T>::W);
-      uint32_t off = st + lane_off;
+      const int nb = bytes_of(K);
+      const int sh = shift_of(K);
       U q0[EPL];
       uint32_t cmin[EPL];
       U run = 0;
       uint32_t cm = 3;
 #pragma unroll
       for (int i = 0; i < EPL; ++i) {
-        const int L = i < cnt ? nb - c[i] : 0;
-        U sv = 0;
-        if (L > 0) sv = (U)(lds_get<U>(s_stage, off) & low_mask<U>(L)) << (8 * c[i]);
-        off += L;
+        int ci = (int)((cw[s] >> (2 * (EPL - 1 - i))) & 3u);
+        ci = ci > nb ? nb : ci;
+        const bool live = i < cnt[s];
+        const int L = live ? nb - ci : 0;
+        const U got = lds_get<U>(s_stage, o < STAGE_WORDS * 4 - 12 ? o : 0);
+        const U sv = (U)((got & low_mask<U>(L)) << (8 * ci));
+        o += L;
         const U stored = byte_swap(sv);
-        // invalid trailing values act as the identity (keep all, add nothing)
-        const int ci = i < cnt ? c[i] : 3;
-        run = (run & top_bytes_mask<U>(ci)) | stored;
-        cm = (uint32_t)ci < cm ? (uint32_t)ci : cm;
+        // values past the end of a short block act as the identity
+        const int cc = live ? ci : 3;
+        run = (run & top_bytes_mask<U>(cc)) | stored;
+        cm = (uint32_t)cc < cm ? (uint32_t)cc : cm;
         q0[i] = run;
         cmin[i] = cm;
       }
@@ -297,21 +426,22 @@ __global__ __launch_bounds__(256) void k_decode(DecodeArgs a) {
       uint32_t pk = top24<U>(run) | cm;
 #pragma unroll
       for (int d = 1; d < LPB; d <<= 1) {
-        const uint32_t o = __shfl_up(pk, d, LPB);
-        if (lig >= d) pk = lead_compose(o, pk);
+        const uint32_t o2 = __shfl_up(pk, d, LPB);
+        pk = lig >= d ? lead_compose(o2, pk) : pk;
       }
       uint32_t carry = __shfl_up(pk, 1, LPB) & 0xFFFFFF00u;
-      if (lig == 0) carry = 0;
+      carry = lig == 0 ? 0u : carry;
       const U cfull = from_top24<U>(carry);
 #pragma unroll
       for (int i = 0; i < EPL; ++i) {
         const U qi = q0[i] | (cfull & top_bytes_mask<U>((int)cmin[i]));
-        v[i] = mu + from_bits<T>((U)(qi << s));
+        v[i] = mu[s] + from_bits<T>((U)(qi << sh));
       }
     }
-    if (cnt > 0) store_run<T, EPL>(y, k * B + (uint64_t)lig * EPL, cnt, v);
-    if (__ballot(bad) != 0 && lane == 0) atomicMax(a.status, kStatusCorrupt);
+    const uint64_t k = (uint64_t)t * TBLK + (uint64_t)s * TB + g;
+    if (cnt[s] > 0) store_run<T, EPL>(y, k * B + (uint64_t)lig * EPL, cnt[s], v);
   }
+  if (__ballot(bad) != 0 && lane == 0) atomicMax(a.status, kStatusCorrupt);
 }
 
 // ---------------------------------------------------------------- launch ---
@@ -319,27 +449,28 @@ __global__ __launch_bounds__(256) void k_decode(DecodeArgs a) {
 template <typename T, int B>
 hipError_t launch_decompress_t(const Job& j, const DecompressLaunch& L, TimerHook hook) {
   using G = Geo<T, B>;
+  constexpr uint32_t CLS = G::TBLK > 1024 ? G::TBLK : 1024;
   const WsLayout W = ws_layout(j.nblk, j.w, j.b);
-  Counters* ctr = reinterpret_cast<Counters*>(L.ws + W.counters);
+  const uint64_t ncls = cdiv(j.nblk, CLS);
+  const uint64_t ntile = cdiv(j.nblk, G::TBLK);
   uint64_t* rank_st = reinterpret_cast<uint64_t*>(L.ws + W.dec_rank);
-  const uint64_t ntile = cdiv(j.nblk, G::TB) + 1;
   // dec_rank and dec_mid are adjacent pieces of the workspace: clear both
-  const uint64_t nclear = (W.total - W.dec_rank) / 8;
+  const uint64_t nclear = (W.dec_mid - W.dec_rank) / 8 + ncls;
   auto run = [&](const char* name, auto&& fn) {
     if (hook) hook(name, L.stream, 1);
     fn();
     if (hook) hook(name, L.stream, 0);
   };
   {
-    const uint32_t grid = (uint32_t)std::min<uint64_t>(cdiv(nclear, 256), 1024);
-    run("k_dinit", [&] { k_dinit<<<grid ? grid : 1, 256, 0, L.stream>>>(ctr, rank_st, nclear, L.status); });
+    const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(cdiv(nclear, 256), 1024));
+    run("k_dinit", [&] { k_dinit<<<grid, 256, 0, L.stream>>>(rank_st, nclear, L.status); });
   }
   DecodeArgs a;
   a.in = (const uint8_t*)L.in;
   a.in_bytes = L.in_bytes;
   a.out = (uint8_t*)L.out;
   a.status = L.status;
-  a.ctr = ctr;
+  a.index = reinterpret_cast<uint64_t*>(L.ws + W.dec_index);
   a.rank_st = rank_st;
   a.mid_st = reinterpret_cast<uint64_t*>(L.ws + W.dec_mid);
   a.n = j.n;
@@ -347,9 +478,10 @@ hipError_t launch_decompress_t(const Job& j, const DecompressLaunch& L, TimerHoo
   a.dtype = j.dtype;
   a.ndims = j.ndims;
   for (int d = 0; d < 4; ++d) a.dims[d] = j.dims[d];
-  (void)ntile;
-  const uint32_t grid = (uint32_t)std::max<uint64_t>(1, cdiv(j.nblk, G::TB));
-  run("k_decode", [&] { k_decode<T, B><<<grid, 256, 0, L.stream>>>(a); });
+  const uint32_t gi = (uint32_t)std::max<uint64_t>(1, ncls);
+  run("k_dindex", [&] { k_dindex<T, B><<<gi, 256, 0, L.stream>>>(a); });
+  const uint32_t gd = (uint32_t)std::max<uint64_t>(1, ntile);
+  run("k_decode", [&] { k_decode<T, B><<<gd, 256, 0, L.stream>>>(a); });
   return hipGetLastError();
 }
 

@@ -46,13 +46,26 @@ struct Traits<double> {
 // Launch geometry that depends only on the block size b: each lane owns EPL
 // consecutive values, LPB lanes share one block, a 256-thread workgroup tile
 // holds TB whole blocks. It changes no output byte.
+// A tile of the encode/decode passes is SUB such rows of TB blocks (about
+// 32 KiB of input, and at least 8 blocks so that a tile owns whole bytes of
+// the state bits), so that the per-tile costs of the prefix sums are rare.
+constexpr int geo_sub(int tile_bytes, int tb) {
+  int s = 32768 / tile_bytes;
+  s = s < 1 ? 1 : s;
+  while (tb * s < 8) s *= 2;
+  return s;
+}
+
 template <typename T, int B>
 struct Geo {
   static constexpr int EPL = B >= 512 ? B / 64 : 8;
   static constexpr int LPB = B / EPL;  // 1..64, divides 64
   static constexpr int TB = kWG / LPB;
-  static constexpr int TILE = TB * B;  // values per tile
+  static constexpr int TILE = TB * B;  // values per row
+  static constexpr int SUB = geo_sub(TILE * (int)sizeof(T), TB);
+  static constexpr int TBLK = TB * SUB;  // blocks per tile
   static_assert(LPB >= 1 && LPB <= 64 && (64 % LPB) == 0, "group must fit a wave");
+  static_assert(TBLK % 8 == 0, "a tile owns whole state bytes");
 };
 
 __device__ __forceinline__ uint32_t bits_of(float v) { return __float_as_uint(v); }
@@ -267,6 +280,39 @@ __device__ __forceinline__ V wg_excl_sum(V v, V* scratch, V& total) {
   return before + inc - v;
 }
 
+// S exclusive prefix sums over the 256 threads at once, laid end to end: the
+// prefix of value s of a thread counts all values s' < s of every thread, then
+// value s of the threads before it. tot[s] receives the total of value s.
+// `scratch` holds S * kWavesPerWG entries. Contains barriers.
+template <int S>
+__device__ __forceinline__ void wg_excl_scan_multi(const uint32_t (&v)[S], uint32_t (&excl)[S],
+                                                   uint32_t (&tot)[S], uint32_t* scratch) {
+  uint32_t inc[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) inc[s] = group_incl_sum<kWave, uint32_t>(v[s]);
+  const int w = threadIdx.x / kWave;
+  if (lane_id() == kWave - 1) {
+#pragma unroll
+    for (int s = 0; s < S; ++s) scratch[s * kWavesPerWG + w] = inc[s];
+  }
+  __syncthreads();
+  uint32_t running = 0;
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int i = 0; i < kWavesPerWG; ++i) {
+      const uint32_t x = scratch[s * kWavesPerWG + i];
+      before += (i < w) ? x : 0u;
+      all += x;
+    }
+    excl[s] = running + before + inc[s] - v[s];
+    tot[s] = all;
+    running += all;
+  }
+  __syncthreads();
+}
+
 // ------------------------------------------------------ decoupled look-back -
 
 // A tile's status word: flag in the top two bits (0 = not yet published,
@@ -287,44 +333,65 @@ __device__ __forceinline__ uint64_t status_load(const uint64_t* p) {
   return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Exclusive prefix of tile t in a device-wide scan over tiles, tile t being
-// workgroup t of the launch. Called by all 64 lanes of one wave; returns the
-// same value in every lane. A tile waits only on lower-numbered tiles, and
-// workgroups start in increasing order on each XCD, so the lowest unfinished
-// tile is always running and every wait ends. The spin is bounded all the
-// same: on exhaustion err is raised to err_code and the partial prefix returned.
-__device__ __noinline__ uint64_t lookback_excl(uint64_t* status, uint32_t t, uint64_t agg,
-                                               uint32_t* err, uint32_t err_code) {
+// Device-wide exclusive prefix sums over tiles (decoupled look-back). A tile
+// first publishes its own aggregate, then resolves its exclusive prefix from
+// its predecessors' words and publishes its inclusive prefix. A tile waits
+// only on lower-numbered tiles; every tile is taken by a running workgroup
+// in increasing order within its ticket class and publishes its aggregate
+// before it waits on anything, so every wait ends. Waits are bounded all the
+// same: on exhaustion err is raised to err_code and the partial prefix is
+// returned.
+__device__ __forceinline__ void lookback_publish(uint64_t* status, uint32_t t, uint64_t agg) {
+  status_store(status + t, (t == 0 ? kFlagIncl : kFlagAgg) | (agg & kValueMask));
+}
+
+// Called by all 64 lanes of one wave after lookback_publish; returns the same
+// exclusive prefix in every lane.
+__device__ __noinline__ uint64_t lookback_resolve(uint64_t* status, uint32_t t, uint64_t agg,
+                                                  uint32_t* err, uint32_t err_code) {
+  constexpr int R = 4;  // status words per lane per round: a window of 256 tiles
   const int lane = lane_id();
-  if (t == 0) {
-    if (lane == 0) status_store(status, kFlagIncl | agg);
-    return 0;
-  }
-  if (lane == 0) status_store(status + t, kFlagAgg | agg);
+  if (t == 0) return 0;
   uint64_t excl = 0;
   int64_t base = (int64_t)t - 1;
   uint32_t spins = 0;
   for (;;) {
-    const int64_t j = base - lane;
-    const uint64_t w = j >= 0 ? status_load(status + j) : (kFlagIncl | 0ull);
-    const uint64_t flag = w >> 62;
-    const uint64_t incl = __ballot(flag == 2);
-    const uint64_t inval = __ballot(flag == 0);
-    const int first = incl ? (int)__ffsll((long long)incl) - 1 : 64;
-    const uint64_t need = first >= 63 ? ~0ull : ((2ull << first) - 1);
-    if (inval & need) {
+    uint64_t w[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const int64_t j = base - (k * kWave + lane);
+      w[k] = j >= 0 ? status_load(status + j) : (kFlagIncl | 0ull);
+    }
+    bool done = false, retry = false;
+    int consumed = 0;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      if (done || retry) continue;
+      const uint64_t flag = w[k] >> 62;
+      const uint64_t incl = __ballot(flag == 2);
+      const uint64_t inval = __ballot(flag == 0);
+      const int first = incl ? (int)__ffsll((long long)incl) - 1 : 64;
+      const uint64_t need = first >= 63 ? ~0ull : ((2ull << first) - 1);
+      if (inval & need) {
+        retry = true;
+        continue;
+      }
+      uint64_t v = lane <= first ? (w[k] & kValueMask) : 0ull;
+      excl += group_sum<kWave, uint64_t>(v);
+      if (first < 64)
+        done = true;
+      else
+        ++consumed;
+    }
+    if (done) break;
+    base -= (int64_t)consumed * kWave;
+    if (retry) {
       if (++spins > kSpinLimit) {
         if (lane == 0) atomicMax(err, err_code);
         break;
       }
       __builtin_amdgcn_s_sleep(1);
-      continue;
     }
-    uint64_t v = lane <= first ? (w & kValueMask) : 0ull;
-    v = group_sum<kWave, uint64_t>(v);
-    excl += v;
-    if (first < 64) break;
-    base -= 64;
   }
   if (lane == 0) status_store(status + t, kFlagIncl | ((excl + agg) & kValueMask));
   return excl;

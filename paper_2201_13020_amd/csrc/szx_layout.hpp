@@ -47,37 +47,51 @@ struct Job {
   uint32_t w;
 };
 
-// Tiles of the classification pass: one block per thread.
-constexpr uint32_t kClsTile = 256;
-
-// Blocks per tile of the encode/decode passes for block size b.
-__host__ __device__ inline uint32_t tile_blocks(uint32_t b) {
+// Blocks per tile of the encode/decode passes for block size b and element
+// size w (mirrors Geo in szx_device.hpp).
+__host__ __device__ inline uint32_t tile_blocks(uint32_t b, uint32_t w) {
   const uint32_t epl = b >= 512 ? b / 64 : 8;
   const uint32_t lpb = b / epl;
-  return 256 / lpb;
+  const uint32_t tb = 256 / lpb;
+  uint32_t sub = 32768 / (tb * b * w);
+  sub = sub < 1 ? 1 : sub;
+  while (tb * sub < 8) sub *= 2;
+  return tb * sub;
 }
 
-// Workspace carve-up; every piece 256-byte aligned.
+// Blocks per tile of the classification pass: a multiple of every encode
+// tile, four blocks per thread at most.
+__host__ __device__ inline uint32_t cls_blocks(uint32_t b, uint32_t w) {
+  const uint32_t t = tile_blocks(b, w);
+  return t > 1024 ? t : 1024;
+}
+
 // Most workgroups of the extrema pass; each leaves its finite range here.
 constexpr uint32_t kMaxRangeParts = 4096;
+// Ticket classes of the persistent encode pass.
+constexpr uint32_t kTicketClasses = 8;
 
+// Workspace carve-up; every piece 256-byte aligned.
 struct WsLayout {
-  uint64_t counters, range_part, stats, rec, cls_status, enc_status, dec_rank, dec_mid, total;
+  uint64_t counters, tickets, range_part, stats, enc_r0, cls_status, enc_mid, dec_index, dec_rank, dec_mid, total;
+  uint64_t ntile, ncls;
 };
 
 __host__ __device__ inline WsLayout ws_layout(uint64_t nblk, uint32_t w, uint32_t b) {
   WsLayout L;
-  const uint64_t ntile = cdiv(nblk, tile_blocks(b)) + 1;
-  const uint64_t ncls = cdiv(nblk, kClsTile) + 1;
+  L.ntile = cdiv(nblk, tile_blocks(b, w)) + 1;
+  L.ncls = cdiv(nblk, cls_blocks(b, w)) + 1;
   L.counters = 0;
-  L.range_part = 256;
+  L.tickets = 256;
+  L.range_part = align256(L.tickets + (uint64_t)kTicketClasses * 256);
   L.stats = align256(L.range_part + (uint64_t)kMaxRangeParts * 16);
-  L.rec = align256(L.stats + nblk * 2 * (uint64_t)w);
-  L.cls_status = align256(L.rec + nblk * 4);
-  L.enc_status = align256(L.cls_status + ncls * 8);
-  L.dec_rank = align256(L.enc_status + ntile * 8);
-  L.dec_mid = align256(L.dec_rank + ntile * 8);
-  L.total = align256(L.dec_mid + ntile * 8);
+  L.enc_r0 = align256(L.stats + nblk * 2 * (uint64_t)w);
+  L.cls_status = align256(L.enc_r0 + L.ntile * 8);
+  L.enc_mid = align256(L.cls_status + L.ncls * 8);
+  L.dec_index = align256(L.enc_mid + L.ntile * 8);
+  L.dec_rank = align256(L.dec_index + L.ntile * 16);
+  L.dec_mid = align256(L.dec_rank + L.ncls * 8);
+  L.total = align256(L.dec_mid + L.ncls * 8);
   return L;
 }
 
