@@ -378,21 +378,36 @@ struct LanePacker {
   }
 };
 
-// Copy the staged bytes [st, st + total) to dst_base + [st, st + total), where
-// dst_base is 16-byte aligned: whole 16-byte chunks as single stores, the
-// shared first and last chunks byte by byte.
-__device__ __forceinline__ void copy_out(uint8_t* __restrict__ dst_base, const uint32_t* stage,
-                                         uint32_t st, uint32_t total) {
+// Copy the staged bytes [0, total) to out + [dst, dst + total): whole aligned
+// 16-byte chunks of the destination as single stores (their bytes realigned
+// from LDS with byte funnel shifts), the shared first and last chunks byte by
+// byte.
+__device__ __forceinline__ void copy_out(uint8_t* __restrict__ out, uint64_t dst, const uint32_t* stage,
+                                         uint32_t total) {
+  const uint32_t st = (uint32_t)(dst & 15u);
+  uint8_t* base = out + (dst - st);
   const uint32_t end = st + total;
   const uint32_t nchunk = (end + 15) / 16;
   for (uint32_t c = threadIdx.x; c < nchunk; c += kWG) {
     const uint32_t lo = c * 16 < st ? st : c * 16;
     const uint32_t hi = c * 16 + 16 > end ? end : c * 16 + 16;
     if (lo == c * 16 && hi == c * 16 + 16) {
-      const uint4 u = reinterpret_cast<const uint4*>(stage)[c];
-      *reinterpret_cast<uint4*>(dst_base + c * 16) = u;
+      const uint32_t p = c * 16 - st;  // stage byte of the chunk's first byte
+      const uint32_t q = p >> 2, sh = p & 3u;
+      uint32_t w[5];
+#pragma unroll
+      for (int i = 0; i < 5; ++i) w[i] = stage[q + i];
+      uint4 u;
+      u.x = __builtin_amdgcn_alignbyte(w[1], w[0], sh);
+      u.y = __builtin_amdgcn_alignbyte(w[2], w[1], sh);
+      u.z = __builtin_amdgcn_alignbyte(w[3], w[2], sh);
+      u.w = __builtin_amdgcn_alignbyte(w[4], w[3], sh);
+      *reinterpret_cast<uint4*>(base + c * 16) = u;
     } else {
-      for (uint32_t i = lo; i < hi; ++i) dst_base[i] = (uint8_t)(stage[i >> 2] >> ((i & 3u) * 8u));
+      for (uint32_t i = lo; i < hi; ++i) {
+        const uint32_t b = i - st;
+        base[i] = (uint8_t)(stage[b >> 2] >> ((b & 3u) * 8u));
+      }
     }
   }
 }
@@ -484,116 +499,88 @@ __global__ __launch_bounds__(256) void k_encode(const T* __restrict__ x, uint8_t
   tile_load<T, B>(cur, t, x, stats, enc_r0, n, nblk, e, s_scan);
 
   for (;;) {
-    // encode the current tile: error control K0, then one more mantissa bit,
-    // then raw. Every lane votes; lanes without a coded block vote yes.
-    U q[SUB][EPL];
-    int Ks[SUB];
-    uint32_t cw[SUB], nbytes[SUB];
+    // Row by row: encode with error control (K0, then one more mantissa bit,
+    // then raw; every lane votes, lanes without a coded block vote yes), codes
+    // and byte counts, the row's offsets, K bytes and codes, and the staged
+    // mid bytes, so that only one row's words are live at a time.
+    uint32_t tile_bytes = 0;
 #pragma unroll
     for (int s = 0; s < SUB; ++s) {
+      U q[EPL];
       int K = cur.K[s];
       const bool coded = K > 0;
       bool ok = encode_try<T, EPL>(cur.x[s], coded ? cur.cnt[s] : 0, cur.mu[s], e, coded ? K : Traits<T>::W,
-                                   coded && cur.verify[s], q[s]);
+                                   coded && cur.verify[s], q);
       if (!group_all<LPB>(ok)) {  // only coded blocks can fail
         const int K1 = kept_bits<T>(K - Traits<T>::KMIN + 1);
         bool ok1 = false;
-        if (K1 != K) ok1 = encode_try<T, EPL>(cur.x[s], cur.cnt[s], cur.mu[s], e, K1, true, q[s]);
+        if (K1 != K) ok1 = encode_try<T, EPL>(cur.x[s], cur.cnt[s], cur.mu[s], e, K1, true, q);
         K = group_all<LPB>(ok1) ? K1 : -1;
       }
       const bool raw = K < 0;
       if (raw) {
 #pragma unroll
-        for (int i = 0; i < EPL; ++i) q[s][i] = bits_of(cur.x[s][i]);
+        for (int i = 0; i < EPL; ++i) q[i] = bits_of(cur.x[s][i]);
       }
-      // 2-bit codes of identical leading bytes and per-value byte counts
-      const int nb = K > 0 ? bytes_of(K) : 0;
-      U prev = __shfl_up(q[s][EPL - 1], 1, LPB);
+      const int nb = raw ? BYTES : (K > 0 ? bytes_of(K) : 0);
+      U prev = __shfl_up(q[EPL - 1], 1, LPB);
       prev = lig == 0 ? (U)0 : prev;
       uint32_t codes = 0, lb = 0;
 #pragma unroll
       for (int i = 0; i < EPL; ++i) {
-        int ci = same_lead_bytes(q[s][i], prev);
+        int ci = same_lead_bytes(q[i], prev);
         ci = ci > 3 ? 3 : ci;
         ci = ci > nb ? nb : ci;
         ci = (K > 0 && i < cur.cnt[s]) ? ci : 0;
         codes |= (uint32_t)ci << (2 * (EPL - 1 - i));
-        prev = q[s][i];
-        lb += i < cur.cnt[s] ? (raw ? BYTES : nb - ci) : 0;
+        prev = q[i];
+        lb += (K != 0 && i < cur.cnt[s]) ? (uint32_t)(nb - ci) : 0u;
       }
-      Ks[s] = K;
-      cw[s] = codes;
-      nbytes[s] = lb;
-    }
-    uint32_t off[SUB], tot[SUB];
-    wg_excl_scan_multi<SUB>(nbytes, off, tot, s_scan);
-    uint32_t tile_bytes = 0;
+      uint32_t rtot;
+      const uint32_t ex = wg_excl_sum<uint32_t>(lb, s_scan, rtot);
+      if (K != 0) {
+        const uint64_t r = cur.r0 + cur.rank[s];
+        const uint64_t k = (uint64_t)t * G::TBLK + (uint64_t)s * G::TB + threadIdx.x / LPB;
+        if (lig == 0) {
+          out[sec.kbytes + r] = raw ? kRawK : (uint8_t)K;
+          if (coded && raw) mus[k] = (T)0;
+        }
+        uint8_t* cdst = out + sec.codes + r * (B / 4) + (uint64_t)lig * (EPL / 4);
+        if constexpr (EPL == 8) {
+          const uint16_t wv = (uint16_t)(((codes >> 8) & 0xFFu) | ((codes & 0xFFu) << 8));
+          *reinterpret_cast<uint16_t*>(cdst) = wv;
+        } else {
 #pragma unroll
-    for (int s = 0; s < SUB; ++s) tile_bytes += tot[s];
+          for (int j = 0; j < EPL / 4; ++j) cdst[j] = (uint8_t)(codes >> (8 * (EPL / 4 - 1 - j)));
+        }
+      }
+      // stage the kept bytes of each value, most significant first
+      LanePacker pk(s_stage, tile_bytes + ex);
+#pragma unroll
+      for (int i = 0; i < EPL; ++i) {
+        const int ci = (int)((codes >> (2 * (EPL - 1 - i))) & 3u);
+        const int Li = (K != 0 && i < cur.cnt[s]) ? nb - ci : 0;
+        const U img = raw ? q[i] : byte_swap(q[i]);
+        const U sv = Li > 0 ? (U)((img >> (8 * ci)) & low_bytes_mask<U>(Li)) : (U)0;
+        pk.put(sv, Li);
+      }
+      pk.flush();
+      tile_bytes += rtot;
+    }
     if (threadIdx.x == 0) lookback_publish(mid_status, t, tile_bytes);
-    const uint64_t r0 = cur.r0;
-    uint32_t rank[SUB];
-    bool rawk[SUB];
-    int cnts[SUB];
-#pragma unroll
-    for (int s = 0; s < SUB; ++s) {
-      rank[s] = cur.rank[s];
-      rawk[s] = cur.K[s] > 0 && Ks[s] < 0;
-      cnts[s] = cur.cnt[s];
-    }
     const uint32_t t_cur = t;
 
     // the next tile's loads go out while this tile's offset is resolved
-    t = claim();
+    t = claim();  // its barriers also order the staging before the copy-out
     const bool more = t < ntiles;
     if (more) tile_load<T, B>(cur, t, x, stats, enc_r0, n, nblk, e, s_scan);
     if (threadIdx.x < kWave) {
       const uint64_t p = lookback_resolve(mid_status, t_cur, tile_bytes, &ctr->err, 1u);
       if (threadIdx.x == 0) s_base = p;
     }
-    // K bytes, codes and the mu of escalated raw blocks
-#pragma unroll
-    for (int s = 0; s < SUB; ++s) {
-      if (Ks[s] != 0) {
-        const uint64_t r = r0 + rank[s];
-        const uint64_t k = (uint64_t)t_cur * G::TBLK + (uint64_t)s * G::TB + threadIdx.x / LPB;
-        if (lig == 0) {
-          out[sec.kbytes + r] = Ks[s] < 0 ? kRawK : (uint8_t)Ks[s];
-          if (rawk[s]) mus[k] = (T)0;
-        }
-        uint8_t* cdst = out + sec.codes + r * (B / 4) + (uint64_t)lig * (EPL / 4);
-        if constexpr (EPL == 8) {
-          const uint16_t wv = (uint16_t)(((cw[s] >> 8) & 0xFFu) | ((cw[s] & 0xFFu) << 8));
-          *reinterpret_cast<uint16_t*>(cdst) = wv;
-        } else {
-#pragma unroll
-          for (int j = 0; j < EPL / 4; ++j) cdst[j] = (uint8_t)(cw[s] >> (8 * (EPL / 4 - 1 - j)));
-        }
-      }
-    }
     __syncthreads();
     const uint64_t base = s_base;
-    const uint64_t gdst = sec.mid + base;
-    const uint32_t st = (uint32_t)(gdst & 15u);
-    // stage the kept bytes of each value, most significant first
-#pragma unroll
-    for (int s = 0; s < SUB; ++s) {
-      const int K = Ks[s];
-      const bool raw = K < 0;
-      const int nb = raw ? BYTES : (K > 0 ? bytes_of(K) : 0);
-      LanePacker pk(s_stage, st + off[s]);
-#pragma unroll
-      for (int i = 0; i < EPL; ++i) {
-        const int ci = raw ? 0 : (int)((cw[s] >> (2 * (EPL - 1 - i))) & 3u);
-        const int Li = (K != 0 && i < cnts[s]) ? nb - ci : 0;
-        const U img = raw ? q[s][i] : byte_swap(q[s][i]);
-        const U sv = Li > 0 ? (U)((img >> (8 * ci)) & low_bytes_mask<U>(Li)) : (U)0;
-        pk.put(sv, Li);
-      }
-      pk.flush();
-    }
-    __syncthreads();
-    copy_out(out + (gdst - st), s_stage, st, tile_bytes);
+    copy_out(out, sec.mid + base, s_stage, tile_bytes);
     if (t_cur == ntiles - 1 && threadIdx.x == 0) ctr->mid_total = base + tile_bytes;
     __syncthreads();
     for (int i = threadIdx.x; i < STAGE_WORDS / 4; i += kWG)

@@ -177,15 +177,21 @@ __device__ __forceinline__ uint32_t block_mid_bytes(const uint8_t* cp, uint32_t 
   }
   const uint32_t nb = (uint32_t)bytes_of((int)Kb);
   uint32_t sum = 0, over = 0;
-  // B/4 code bytes, 4 codes per byte, first value in the top bits
-  for (uint32_t j = 0; j < (uint32_t)B / 4; j += 4) {
-    // the block's own code bytes only (b = 8 has two)
-    uint32_t w = 0;
+  // B/4 code bytes, 4 codes per byte, first value in the top bits; read in
+  // aligned words of 16 codes (b = 8 has one half word)
+  constexpr uint32_t NW = B >= 16 ? B / 16 : 1;
 #pragma unroll
-    for (uint32_t q = 0; q < 4; ++q) w |= (j + q < (uint32_t)B / 4 ? (uint32_t)cp[j + q] : 0u) << (24 - 8 * q);
-    const uint32_t first = 4 * j;  // value index of the top code of w
-    if (first >= nk) break;
-    if (nk - first < 16) w &= ~0u << (2 * (16 - (nk - first)));  // codes past the block end
+  for (uint32_t j = 0; j < NW; ++j) {
+    uint32_t w;
+    if constexpr (B >= 16) {
+      w = __builtin_bswap32(reinterpret_cast<const uint32_t*>(cp)[j]);
+    } else {
+      const uint32_t h2 = *reinterpret_cast<const uint16_t*>(cp);
+      w = ((h2 & 0xFFu) << 24) | ((h2 >> 8) << 16);
+    }
+    const uint32_t first = 16 * j;  // value index of the top code of w
+    if (first >= nk) w = 0;
+    else if (nk - first < 16) w &= ~0u << (2 * (16 - (nk - first)));  // codes past the block end
     sum += __popc(w & 0x55555555u) + 2u * __popc(w & 0xAAAAAAAAu);
     over |= w & (w >> 1) & 0x55555555u;  // a code of 3
   }
@@ -354,7 +360,7 @@ __global__ __launch_bounds__(256) void k_decode(DecodeArgs a) {
     }
     const int nb = K > 0 ? bytes_of(K) : 0;
     uint32_t c = 0;
-    if (K > 0) {
+    if (have) {  // loaded beside K, used only for a coded block
       const uint8_t* cp = in + h.sec.codes + r * (B / 4) + (uint64_t)lig * (EPL / 4);
       if constexpr (EPL == 8) {
         const uint32_t v16 = *reinterpret_cast<const uint16_t*>(cp);
@@ -364,6 +370,7 @@ __global__ __launch_bounds__(256) void k_decode(DecodeArgs a) {
         for (int j = 0; j < EPL / 4; ++j) c = (c << 8) | cp[j];
       }
     }
+    c = K > 0 ? c : 0u;
     uint32_t lb = 0;
 #pragma unroll
     for (int i = 0; i < EPL; ++i) {
