@@ -31,8 +31,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
-BOUNDS = (1e-2, 1e-3, 1e-4)
 BLOCK = 128
+# bench fields: the headline is cfg2; the others are for design measurements
+FIELDS = {
+    "cfg2": dict(shape=(100, 500, 500), bounds=(1e-2, 1e-3, 1e-4),
+                 desc="100x500x500 float32 turbulence field with 20% zero regions"),
+    "cfg3b": dict(shape=(1 << 28,), bounds=(1e-3, 1e-5),
+                  desc="2^28 float64 state vector (exp-decaying complex amplitudes)"),
+    "cfg3a": dict(shape=(1800, 3600), bounds=(1e-3, 1e-5), desc="1800x3600 float32 spherical-harmonic field"),
+    "cfg1": dict(shape=(1 << 20,), bounds=(1e-3,), desc="2^20 float32 sum of sines"),
+}
+BOUNDS = FIELDS["cfg2"]["bounds"]
 
 
 def parse():
@@ -45,7 +54,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile", action="store_true",
                     help="short eager run for profilers: no CPU baseline, no instrumented pass, plus a plain 256 MiB copy whose HBM counters scale the others")
-    ap.add_argument("--shape", type=str, default="100,500,500")
+    ap.add_argument("--field", type=str, default="cfg2", choices=sorted(FIELDS))
     return ap.parse_args()
 
 
@@ -111,21 +120,26 @@ def main():
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     dev = torch.device("cuda:0")
-    shape = tuple(int(s) for s in args.shape.split(","))
-    x_np = synth.turbulence_3d(shape)
+    global BOUNDS
+    field = FIELDS[args.field]
+    BOUNDS = field["bounds"]
+    shape = field["shape"]
+    x_np = synth.make(args.field)
     n = x_np.size
     w = x_np.itemsize
     nbytes = n * w
-    C = max(1, args.copies)
+    tdt = torch.float32 if w == 4 else torch.float64
+    # copies so that the inputs exceed the 256 MB last-level cache
+    C = max(1, args.copies if nbytes < (1 << 30) else 2)
     xs = [torch.from_numpy(x_np).to(dev) for _ in range(C)]
-    cap = szx.compress_bound(torch.float32, shape, 1e-3, "rel", BLOCK)
-    wsz = szx.workspace_size(torch.float32, shape, 1e-3, "rel", BLOCK)
+    cap = szx.compress_bound(tdt, shape, 1e-3, "rel", BLOCK)
+    wsz = szx.workspace_size(tdt, shape, 1e-3, "rel", BLOCK)
     outs = {eb: [torch.empty(cap, dtype=torch.uint8, device=dev) for _ in range(C)] for eb in BOUNDS}
     sizes = {eb: [torch.zeros(1, dtype=torch.uint64, device=dev) for _ in range(C)] for eb in BOUNDS}
-    ys = [torch.empty(n, dtype=torch.float32, device=dev) for _ in range(C)]
+    ys = [torch.empty(n, dtype=tdt, device=dev) for _ in range(C)]
     stat = torch.zeros(1, dtype=torch.uint32, device=dev)
     ws = torch.empty(wsz, dtype=torch.uint8, device=dev)
-    expected = dict(dtype=torch.float32, dims=shape, block=BLOCK)
+    expected = dict(dtype=tdt, dims=shape, block=BLOCK)
 
     # first pass: stream sizes (the decoder reads only what the header says,
     # but the in_bytes argument must cover the stream)
@@ -167,15 +181,16 @@ def main():
             gpu_stream = outs[eb][0][: stream_len[eb]].cpu().numpy()
             assert gpu_stream.size == ref.size and np.array_equal(gpu_stream, ref), f"GPU stream differs from the oracle at eb={eb}"
         y_last = ys[0].cpu().numpy()
-        assert np.array_equal(y_last.view(np.uint32), yref.ravel().view(np.uint32)), "GPU decode differs from the oracle"
+        udt = np.uint32 if w == 4 else np.uint64
+        assert np.array_equal(y_last.view(udt), yref.ravel().view(udt)), "GPU decode differs from the oracle"
         cpu = {
-            "value": round(3 * nbytes / (t_c + t_d) / 1e9, 4),
+            "value": round(len(BOUNDS) * nbytes / (t_c + t_d) / 1e9, 4),
             "unit": "GB/s",
             "cores": 1,
             "kind": "oracle",
-            "sample": f"whole workload once: {'x'.join(map(str, shape))} float32, REL {', '.join(map(str, BOUNDS))}, "
-                      f"compress + decompress each, single thread; compress {3 * nbytes / t_c / 1e6:.0f} MB/s, "
-                      f"decompress {3 * nbytes / t_d / 1e6:.0f} MB/s",
+            "sample": f"whole workload once: {field['desc']}, REL {', '.join(map(str, BOUNDS))}, "
+                      f"compress + decompress each, single thread; compress {len(BOUNDS) * nbytes / t_c / 1e6:.0f} MB/s, "
+                      f"decompress {len(BOUNDS) * nbytes / t_d / 1e6:.0f} MB/s",
             "seconds": round(t_c + t_d, 3),
         }
 
@@ -215,7 +230,7 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_per_step = elapsed * 1e3 / args.steps
-    value = 3 * nbytes / (elapsed / args.steps) / 1e9
+    value = len(BOUNDS) * nbytes / (elapsed / args.steps) / 1e9
 
     # check the last replays decoded correctly (status and a spot check)
     assert int(stat.cpu().view(torch.int32).item()) == 0
@@ -231,11 +246,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if w == 4 else "f64",
         "data": "synthetic",
-        "config": {"workload": f"{'x'.join(map(str, shape))} float32 turbulence field with 20% zero regions, "
-                               f"REL {', '.join(map(str, BOUNDS))}, block {BLOCK}; one step = compress + decompress at each bound",
-                   "global_batch": 3, "elements": n, "block": BLOCK, "parallelism": "single GPU",
+        "config": {"workload": f"{field['desc']}, REL {', '.join(map(str, BOUNDS))}, block {BLOCK}; "
+                               "one step = compress + decompress at each bound",
+                   "global_batch": len(BOUNDS), "elements": n, "block": BLOCK, "parallelism": "single GPU",
                    "launch": "eager" if graphs is None else "hip graph replay", "input_copies": C},
     }
 
@@ -294,7 +309,7 @@ def main():
         result["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": kd["achieved_GBps"],
                               "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                               "frac": round(kd["achieved_GBps"] / HBM_PEAK_GBPS, 4),
-                              "traffic": recorded_traffic(dom),
+                              "traffic": recorded_traffic(dom, args.field),
                               "alg_bytes_per_launch": kd["alg_bytes_per_launch"], "avg_launch_us": kd["avg_us"]}
     if cpu is not None:
         result["cpu_baseline"] = cpu

@@ -245,3 +245,23 @@ def test_graph_replays_match_eager():
         # unrelated eager work on the same workspace between replays
         o2, s2 = szx.compress(other, 1e-2, "rel", 64)
         torch.cuda.synchronize()
+
+
+_CFG3B = {}
+
+
+def _cfg3b():
+    if "x" not in _CFG3B:
+        from paper_2201_13020_amd import synth
+        _CFG3B["x"] = synth.make("cfg3b")
+    return _CFG3B["x"]
+
+
+@pytest.mark.parametrize("eb", [1e-3, 1e-5])
+def test_parity_cfg3b_full(eb):
+    """2^28 float64 values (2 GiB): byte-exact stream and bit-exact values."""
+    x = _cfg3b()
+    ref = check_parity(x, eb, "rel", 128, "cfg3b")
+    info = sf.parse(ref)
+    print(f"[cfg3b] eb={eb} CR={x.nbytes / ref.size:.3f} constant blocks "
+          f"{1 - info['n_nc'] / info['nblk']:.3f}", flush=True)
