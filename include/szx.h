@@ -109,6 +109,60 @@ sz_status sz_decompress(const void* d_in, uint64_t in_bytes,
                         uint32_t* d_status, void* d_ws, uint64_t ws_bytes,
                         hipStream_t stream);
 
+/* ---- batches (many fields, one launch per pass) ---------------------------
+   A batch compresses (or decompresses) many fields of mixed element types,
+   sizes and bounds with one launch per pass over all of them: one extrema
+   launch, one range launch, one classification launch, one persistent encode
+   launch (float32 tiles of every field, then float64 tiles), one finalize
+   launch. Each field's stream is byte-identical to what sz_compress writes
+   for it alone (the single call runs the same kernels as a batch of one).
+   All fields of a batch share one block size. The batch's descriptor table
+   and tile maps live in its workspace: sz_batch_create_* writes them there
+   once (a synchronous copy; call it outside graph capture), then every
+   sz_batch_run enqueues kernels only (asynchronous, allocation-free,
+   graph-capturable). The buffers named in the fields must stay valid and the
+   workspace untouched for the life of the batch. */
+typedef struct {
+  sz_params params;      /* as for sz_compress */
+  const void* d_in;      /* device, 16-byte aligned */
+  void* d_out;           /* device, 16-byte aligned, out_cap bytes */
+  uint64_t out_cap;      /* >= sz_compress_bound(&params) */
+  uint64_t* d_out_size;  /* device u64: stream size, 0 on device failure */
+} sz_cfield;
+
+typedef struct {
+  sz_params expected;  /* as for sz_decompress */
+  const void* d_in;    /* device stream, 16-byte aligned */
+  uint64_t in_bytes;
+  void* d_out;         /* device, 16-byte aligned, out_cap bytes */
+  uint64_t out_cap;    /* >= N * sizeof(T) */
+  uint32_t* d_status;  /* device u32, as for sz_decompress */
+} sz_dfield;
+
+typedef struct sz_batch_s* sz_batch;
+
+/* Workspace bytes of a compression batch (cf) or a decompression batch (df);
+   exactly one of cf, df is non-null. 0 for invalid fields. Host only. */
+uint64_t sz_batch_workspace_size(const sz_cfield* cf, const sz_dfield* df, uint32_t n);
+
+/* Plan a batch into the device workspace d_ws (16-byte aligned, ws_bytes >=
+   sz_batch_workspace_size). Errors: SZ_EINVAL (bad field, mixed block sizes),
+   SZ_ENOSPC, SZ_EUNSUPPORTED, SZ_EDEVICE. */
+sz_status sz_batch_create_compress(const sz_cfield* fields, uint32_t n, void* d_ws, uint64_t ws_bytes,
+                                   sz_batch* out);
+sz_status sz_batch_create_decompress(const sz_dfield* fields, uint32_t n, void* d_ws, uint64_t ws_bytes,
+                                     sz_batch* out);
+
+/* Launch geometry of a compression batch: persistent workgroups of the encode
+   pass (the autotuner's knob; no effect on the output bytes). */
+sz_status sz_batch_set_geometry(sz_batch b, uint32_t encode_wgs);
+
+/* Enqueue every pass of the batch on `stream`. */
+sz_status sz_batch_run(sz_batch b, hipStream_t stream);
+
+/* Release the host handle (the workspace stays the caller's). */
+void sz_batch_destroy(sz_batch b);
+
 /* Parse a host copy of a stream header (at least 96 bytes). Fills *out and
    *total_bytes (the full stream size). Returns SZ_ECORRUPT for a bad header,
    SZ_EINVAL for null pointers. Host only. */

@@ -102,6 +102,299 @@ szx::TimerHook current_hook() {
   return g_timing ? timer_hook : nullptr;
 }
 
+// ---- descriptors --------------------------------------------------------
+
+// Descriptor of one compression field whose workspace pieces come from the
+// single-field layout at ws.
+szx::FieldC single_field_c(const szx::Job& j, const void* in, void* out, uint64_t* out_size, uint8_t* ws) {
+  const szx::WsLayout W = szx::ws_layout(j.n, j.nblk, j.w, j.b);
+  const szx::FieldTiles ft = szx::field_tiles(j.n, j.nblk, j.w, j.b);
+  szx::FieldC f;
+  memset(&f, 0, sizeof f);
+  f.in = in;
+  f.out = (uint8_t*)out;
+  f.out_size = out_size;
+  f.n = j.n;
+  f.nblk = j.nblk;
+  f.mu_off = szx::sections(j.nblk, 0, j.w, j.b, 0).mu;
+  for (int d = 0; d < 4; ++d) f.dims[d] = j.dims[d];
+  f.eb = j.eb;
+  f.dtype = j.dtype;
+  f.eb_mode = j.eb_mode;
+  f.ndims = j.ndims;
+  f.b = j.b;
+  f.ctr = (szx::Counters*)(ws + W.counters);
+  f.stats = ws + W.stats;
+  f.part = (uint64_t*)(ws + W.part);
+  f.enc_r0 = (uint64_t*)(ws + W.enc_r0);
+  f.cls_status = (uint64_t*)(ws + W.cls_status);
+  f.enc_mid = (uint64_t*)(ws + W.enc_mid);
+  f.nparts = (uint32_t)ft.chunks;
+  return f;
+}
+
+szx::FieldD single_field_d(const szx::Job& j, const void* in, uint64_t in_bytes, void* out, uint32_t* status,
+                           uint8_t* ws) {
+  const szx::WsLayout W = szx::ws_layout(j.n, j.nblk, j.w, j.b);
+  szx::FieldD f;
+  memset(&f, 0, sizeof f);
+  f.in = (const uint8_t*)in;
+  f.in_bytes = in_bytes;
+  f.out = (uint8_t*)out;
+  f.status = status;
+  f.index = (uint64_t*)(ws + W.dec_index);
+  f.rank_st = (uint64_t*)(ws + W.dec_rank);
+  f.mid_st = (uint64_t*)(ws + W.dec_mid);
+  f.n = j.n;
+  f.nblk = j.nblk;
+  f.dtype = j.dtype;
+  f.ndims = j.ndims;
+  for (int d = 0; d < 4; ++d) f.dims[d] = j.dims[d];
+  return f;
+}
+
+szx::CLaunchGeom default_geom(int ncu) {
+  szx::CLaunchGeom g;
+  g.encode_wgs = (uint32_t)ncu * 4;
+  return g;
+}
+
+}  // namespace
+
+// Host handle of a planned batch (descriptors already in the workspace).
+struct sz_batch_s {
+  int decompress;
+  uint32_t block;
+  szx::CBatch cb;
+  szx::DBatch db;
+  szx::CLaunchGeom geom;
+};
+
+namespace {
+
+uint64_t a256(uint64_t x) { return szx::align256(x); }
+
+// Byte layout of a batch workspace; fills descriptors when `host` is given.
+// Map m = 2 * pass + element type; compress passes: extrema chunks,
+// classification, encode; decompress passes: index, decode.
+struct BatchPlan {
+  uint64_t fields_off, maps_off[6], zero_off, zero_end, total;
+  uint64_t tiles[6];
+  int nmaps;
+};
+
+sz_status check_batch_common(uint32_t n, uint32_t block, const sz_params* p) {
+  if (n == 0) return fail(SZ_EINVAL, "empty batch");
+  if (p->block_size != block) return fail(SZ_EINVAL, "all fields of a batch share one block size");
+  return SZ_OK;
+}
+
+sz_status plan_compress(const sz_cfield* fs, uint32_t n, uint8_t* ws, std::vector<uint8_t>* host, BatchPlan& P,
+                        sz_batch_s* hb) {
+  if (!fs || n == 0) return fail(SZ_EINVAL, "empty batch");
+  std::vector<szx::Job> jobs(n);
+  const uint32_t block = fs[0].params.block_size;
+  P.nmaps = 6;
+  for (int m = 0; m < 6; ++m) P.tiles[m] = 0;
+  for (uint32_t i = 0; i < n; ++i) {
+    sz_status s = make_job(&fs[i].params, jobs[i]);
+    if (s != SZ_OK) return s;
+    s = check_batch_common(n, block, &fs[i].params);
+    if (s != SZ_OK) return s;
+    const szx::FieldTiles ft = szx::field_tiles(jobs[i].n, jobs[i].nblk, jobs[i].w, block);
+    const uint32_t dt = jobs[i].dtype;
+    P.tiles[0 + dt] += ft.chunks;
+    P.tiles[2 + dt] += ft.cls;
+    P.tiles[4 + dt] += ft.enc;
+  }
+  uint64_t off = 256;
+  P.fields_off = off;
+  off = a256(off + (uint64_t)n * sizeof(szx::FieldC));
+  for (int m = 0; m < 6; ++m) {
+    P.maps_off[m] = off;
+    off = a256(off + P.tiles[m] * 4);
+  }
+  P.zero_off = off;
+  off = a256(off + 2ull * szx::kTicketClasses * 256);  // tickets
+  std::vector<uint64_t> ctr_off(n), cls_off(n), mid_off(n);
+  for (uint32_t i = 0; i < n; ++i) {
+    const szx::FieldTiles ft = szx::field_tiles(jobs[i].n, jobs[i].nblk, jobs[i].w, block);
+    ctr_off[i] = off;
+    off = a256(off + 256);
+    cls_off[i] = off;
+    off = a256(off + (ft.cls + 1) * 8);
+    mid_off[i] = off;
+    off = a256(off + (ft.enc + 1) * 8);
+  }
+  P.zero_end = off;
+  std::vector<uint64_t> part_off(n), stats_off(n), r0_off(n);
+  for (uint32_t i = 0; i < n; ++i) {
+    const szx::FieldTiles ft = szx::field_tiles(jobs[i].n, jobs[i].nblk, jobs[i].w, block);
+    part_off[i] = off;
+    off = a256(off + (ft.chunks + 1) * 16);
+    stats_off[i] = off;
+    off = a256(off + jobs[i].nblk * 2 * (uint64_t)jobs[i].w);
+    r0_off[i] = off;
+    off = a256(off + (ft.enc + 1) * 8);
+  }
+  P.total = off;
+  if (!host) return SZ_OK;
+  host->assign(P.zero_off, 0);
+  szx::FieldC* F = (szx::FieldC*)(host->data() + P.fields_off);
+  uint32_t* maps[6];
+  for (int m = 0; m < 6; ++m) maps[m] = (uint32_t*)(host->data() + P.maps_off[m]);
+  uint64_t bc[2] = {0, 0}, bl[2] = {0, 0}, be[2] = {0, 0};
+  for (uint32_t i = 0; i < n; ++i) {
+    const szx::Job& j = jobs[i];
+    const sz_cfield& c = fs[i];
+    if ((!c.d_in && j.n) || !c.d_out || !c.d_out_size) return fail(SZ_EINVAL, "null buffer in batch");
+    if (!aligned16(c.d_in) || !aligned16(c.d_out)) return fail(SZ_EINVAL, "batch buffers must be 16-byte aligned");
+    if (c.out_cap < szx::sections(j.nblk, j.nblk, j.w, j.b, j.n * j.w).total)
+      return fail(SZ_ENOSPC, "a batch output capacity is below sz_compress_bound");
+    const szx::FieldTiles ft = szx::field_tiles(j.n, j.nblk, j.w, block);
+    szx::FieldC f;
+    memset(&f, 0, sizeof f);
+    f.in = c.d_in;
+    f.out = (uint8_t*)c.d_out;
+    f.out_size = c.d_out_size;
+    f.n = j.n;
+    f.nblk = j.nblk;
+    f.mu_off = szx::sections(j.nblk, 0, j.w, j.b, 0).mu;
+    for (int d = 0; d < 4; ++d) f.dims[d] = j.dims[d];
+    f.eb = j.eb;
+    f.dtype = j.dtype;
+    f.eb_mode = j.eb_mode;
+    f.ndims = j.ndims;
+    f.b = j.b;
+    f.ctr = (szx::Counters*)(ws + ctr_off[i]);
+    f.stats = ws + stats_off[i];
+    f.part = (uint64_t*)(ws + part_off[i]);
+    f.enc_r0 = (uint64_t*)(ws + r0_off[i]);
+    f.cls_status = (uint64_t*)(ws + cls_off[i]);
+    f.enc_mid = (uint64_t*)(ws + mid_off[i]);
+    f.nparts = (uint32_t)ft.chunks;
+    const uint32_t dt = j.dtype;
+    f.base_stats = bc[dt];
+    f.base_cls = bl[dt];
+    f.base_enc = be[dt];
+    F[i] = f;
+    for (uint64_t t = 0; t < ft.chunks; ++t) maps[0 + dt][bc[dt] + t] = i;
+    for (uint64_t t = 0; t < ft.cls; ++t) maps[2 + dt][bl[dt] + t] = i;
+    for (uint64_t t = 0; t < ft.enc; ++t) maps[4 + dt][be[dt] + t] = i;
+    bc[dt] += ft.chunks;
+    bl[dt] += ft.cls;
+    be[dt] += ft.enc;
+  }
+  szx::CBatch& b = hb->cb;
+  memset(&b, 0, sizeof b);
+  b.fields = (const szx::FieldC*)(ws + P.fields_off);
+  for (int dt = 0; dt < 2; ++dt) {
+    b.field_stats[dt] = (const uint32_t*)(ws + P.maps_off[0 + dt]);
+    b.field_cls[dt] = (const uint32_t*)(ws + P.maps_off[2 + dt]);
+    b.field_enc[dt] = (const uint32_t*)(ws + P.maps_off[4 + dt]);
+    b.tiles_stats[dt] = P.tiles[0 + dt];
+    b.tiles_cls[dt] = P.tiles[2 + dt];
+    b.tiles_enc[dt] = P.tiles[4 + dt];
+  }
+  b.tickets = (uint32_t*)(ws + P.zero_off);
+  b.zero_begin = (uint64_t*)(ws + P.zero_off);
+  b.zero_words = (P.zero_end - P.zero_off) / 8;
+  b.nfields = n;
+  hb->block = block;
+  return SZ_OK;
+}
+
+sz_status plan_decompress(const sz_dfield* fs, uint32_t n, uint8_t* ws, std::vector<uint8_t>* host, BatchPlan& P,
+                          sz_batch_s* hb) {
+  if (!fs || n == 0) return fail(SZ_EINVAL, "empty batch");
+  std::vector<szx::Job> jobs(n);
+  const uint32_t block = fs[0].expected.block_size;
+  P.nmaps = 4;
+  for (int m = 0; m < 6; ++m) P.tiles[m] = 0;
+  for (uint32_t i = 0; i < n; ++i) {
+    sz_status s = make_job(&fs[i].expected, jobs[i]);
+    if (s != SZ_OK) return s;
+    s = check_batch_common(n, block, &fs[i].expected);
+    if (s != SZ_OK) return s;
+    const szx::FieldTiles ft = szx::field_tiles(jobs[i].n, jobs[i].nblk, jobs[i].w, block);
+    P.tiles[0 + jobs[i].dtype] += ft.cls;
+    P.tiles[2 + jobs[i].dtype] += ft.enc;
+  }
+  uint64_t off = 256;
+  P.fields_off = off;
+  off = a256(off + (uint64_t)n * sizeof(szx::FieldD));
+  for (int m = 0; m < 4; ++m) {
+    P.maps_off[m] = off;
+    off = a256(off + P.tiles[m] * 4);
+  }
+  P.zero_off = off;
+  std::vector<uint64_t> rank_off(n), mid_off(n), index_off(n);
+  for (uint32_t i = 0; i < n; ++i) {
+    const szx::FieldTiles ft = szx::field_tiles(jobs[i].n, jobs[i].nblk, jobs[i].w, block);
+    rank_off[i] = off;
+    off = a256(off + (ft.cls + 1) * 8);
+    mid_off[i] = off;
+    off = a256(off + (ft.cls + 1) * 8);
+  }
+  P.zero_end = off;
+  for (uint32_t i = 0; i < n; ++i) {
+    const szx::FieldTiles ft = szx::field_tiles(jobs[i].n, jobs[i].nblk, jobs[i].w, block);
+    index_off[i] = off;
+    off = a256(off + (ft.enc + 1) * 16);
+  }
+  P.total = off;
+  if (!host) return SZ_OK;
+  host->assign(P.zero_off, 0);
+  szx::FieldD* F = (szx::FieldD*)(host->data() + P.fields_off);
+  uint32_t* maps[4];
+  for (int m = 0; m < 4; ++m) maps[m] = (uint32_t*)(host->data() + P.maps_off[m]);
+  uint64_t bi[2] = {0, 0}, bd[2] = {0, 0};
+  for (uint32_t i = 0; i < n; ++i) {
+    const szx::Job& j = jobs[i];
+    const sz_dfield& d = fs[i];
+    if (!d.d_in || (!d.d_out && j.n) || !d.d_status) return fail(SZ_EINVAL, "null buffer in batch");
+    if (!aligned16(d.d_in) || !aligned16(d.d_out)) return fail(SZ_EINVAL, "batch buffers must be 16-byte aligned");
+    if (d.out_cap < j.n * j.w) return fail(SZ_ENOSPC, "a batch output capacity is below N * sizeof(T)");
+    const szx::FieldTiles ft = szx::field_tiles(j.n, j.nblk, j.w, block);
+    szx::FieldD f;
+    memset(&f, 0, sizeof f);
+    f.in = (const uint8_t*)d.d_in;
+    f.in_bytes = d.in_bytes;
+    f.out = (uint8_t*)d.d_out;
+    f.status = d.d_status;
+    f.index = (uint64_t*)(ws + index_off[i]);
+    f.rank_st = (uint64_t*)(ws + rank_off[i]);
+    f.mid_st = (uint64_t*)(ws + mid_off[i]);
+    f.n = j.n;
+    f.nblk = j.nblk;
+    f.dtype = j.dtype;
+    f.ndims = j.ndims;
+    for (int k = 0; k < 4; ++k) f.dims[k] = j.dims[k];
+    const uint32_t dt = j.dtype;
+    f.base_idx = bi[dt];
+    f.base_dec = bd[dt];
+    F[i] = f;
+    for (uint64_t t = 0; t < ft.cls; ++t) maps[0 + dt][bi[dt] + t] = i;
+    for (uint64_t t = 0; t < ft.enc; ++t) maps[2 + dt][bd[dt] + t] = i;
+    bi[dt] += ft.cls;
+    bd[dt] += ft.enc;
+  }
+  szx::DBatch& b = hb->db;
+  memset(&b, 0, sizeof b);
+  b.fields = (const szx::FieldD*)(ws + P.fields_off);
+  for (int dt = 0; dt < 2; ++dt) {
+    b.field_idx[dt] = (const uint32_t*)(ws + P.maps_off[0 + dt]);
+    b.field_dec[dt] = (const uint32_t*)(ws + P.maps_off[2 + dt]);
+    b.tiles_idx[dt] = P.tiles[0 + dt];
+    b.tiles_dec[dt] = P.tiles[2 + dt];
+  }
+  b.zero_begin = (uint64_t*)(ws + P.zero_off);
+  b.zero_words = (P.zero_end - P.zero_off) / 8;
+  b.nfields = n;
+  hb->block = block;
+  return SZ_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -115,7 +408,7 @@ uint64_t sz_compress_bound(const sz_params* p) {
 uint64_t sz_workspace_size(const sz_params* p) {
   szx::Job j;
   if (make_job(p, j) != SZ_OK) return 0;
-  return szx::ws_layout(j.nblk, j.w, j.b).total;
+  return szx::ws_layout(j.n, j.nblk, j.w, j.b).total;
 }
 
 sz_status sz_compress(const sz_params* p, const void* d_in, void* d_out, uint64_t out_cap,
@@ -131,8 +424,20 @@ sz_status sz_compress(const sz_params* p, const void* d_in, void* d_out, uint64_
   if (ws_bytes < sz_workspace_size(p)) return fail(SZ_ENOSPC, "workspace below sz_workspace_size");
   const int ncu = cu_count();
   if (ncu <= 0) return fail(SZ_EDEVICE, "no HIP device");
-  szx::CompressLaunch L{d_in, (uint8_t*)d_out, d_out_size, (uint8_t*)d_ws, ncu, stream};
-  const hipError_t e = szx::launch_compress(j, L, current_hook());
+  uint8_t* ws = (uint8_t*)d_ws;
+  const szx::WsLayout W = szx::ws_layout(j.n, j.nblk, j.w, j.b);
+  const szx::FieldTiles ft = szx::field_tiles(j.n, j.nblk, j.w, j.b);
+  szx::CBatch b;
+  memset(&b, 0, sizeof b);
+  b.one = single_field_c(j, d_in, d_out, d_out_size, ws);
+  b.tiles_stats[j.dtype] = ft.chunks;
+  b.tiles_cls[j.dtype] = ft.cls;
+  b.tiles_enc[j.dtype] = ft.enc;
+  b.tickets = (uint32_t*)(ws + W.tickets);
+  b.zero_begin = (uint64_t*)(ws + W.counters);
+  b.zero_words = (W.zero_end - W.counters) / 8;
+  b.nfields = 1;
+  const hipError_t e = szx::launch_compress(b, j.b, default_geom(ncu), stream, current_hook());
   if (e != hipSuccess) return fail(SZ_EDEVICE, std::string("launch failed: ") + hipGetErrorString(e));
   return SZ_OK;
 }
@@ -151,11 +456,84 @@ sz_status sz_decompress(const void* d_in, uint64_t in_bytes, const sz_params* ex
   if (ws_bytes < sz_workspace_size(expected)) return fail(SZ_ENOSPC, "workspace below sz_workspace_size");
   const int ncu = cu_count();
   if (ncu <= 0) return fail(SZ_EDEVICE, "no HIP device");
-  szx::DecompressLaunch L{d_in, in_bytes, d_out, d_status, (uint8_t*)d_ws, ncu, stream};
-  const hipError_t e = szx::launch_decompress(j, L, current_hook());
+  uint8_t* ws = (uint8_t*)d_ws;
+  const szx::WsLayout W = szx::ws_layout(j.n, j.nblk, j.w, j.b);
+  const szx::FieldTiles ft = szx::field_tiles(j.n, j.nblk, j.w, j.b);
+  szx::DBatch b;
+  memset(&b, 0, sizeof b);
+  b.one = single_field_d(j, d_in, in_bytes, d_out, d_status, ws);
+  b.tiles_idx[j.dtype] = ft.cls;
+  b.tiles_dec[j.dtype] = ft.enc;
+  b.zero_begin = (uint64_t*)(ws + W.dec_rank);
+  b.zero_words = (W.zero_end - W.dec_rank) / 8;
+  b.nfields = 1;
+  const hipError_t e = szx::launch_decompress(b, j.b, stream, current_hook());
   if (e != hipSuccess) return fail(SZ_EDEVICE, std::string("launch failed: ") + hipGetErrorString(e));
   return SZ_OK;
 }
+
+uint64_t sz_batch_workspace_size(const sz_cfield* cf, const sz_dfield* df, uint32_t n) {
+  BatchPlan P;
+  sz_batch_s tmp;
+  if ((cf != nullptr) == (df != nullptr)) return 0;
+  const sz_status s = cf ? plan_compress(cf, n, nullptr, nullptr, P, &tmp) : plan_decompress(df, n, nullptr, nullptr, P, &tmp);
+  return s == SZ_OK ? P.total : 0;
+}
+
+static sz_status batch_create(const sz_cfield* cf, const sz_dfield* df, uint32_t n, void* d_ws, uint64_t ws_bytes,
+                              sz_batch* out) {
+  g_err.clear();
+  if (!out || !d_ws) return fail(SZ_EINVAL, "null pointer");
+  if (!aligned16(d_ws)) return fail(SZ_EINVAL, "workspace must be 16-byte aligned");
+  const int ncu = cu_count();
+  if (ncu <= 0) return fail(SZ_EDEVICE, "no HIP device");
+  sz_batch_s* hb = new sz_batch_s;
+  memset(hb, 0, sizeof *hb);
+  hb->decompress = df != nullptr;
+  hb->geom = default_geom(ncu);
+  BatchPlan P;
+  std::vector<uint8_t> host;
+  sz_status s = cf ? plan_compress(cf, n, (uint8_t*)d_ws, &host, P, hb) : plan_decompress(df, n, (uint8_t*)d_ws, &host, P, hb);
+  if (s == SZ_OK && ws_bytes < P.total) s = fail(SZ_ENOSPC, "workspace below sz_batch_workspace_size");
+  if (s == SZ_OK) {
+    // descriptors and tile maps, once; run() launches kernels only
+    const hipError_t e = hipMemcpy(d_ws, host.data(), host.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) s = fail(SZ_EDEVICE, std::string("descriptor upload failed: ") + hipGetErrorString(e));
+  }
+  if (s != SZ_OK) {
+    delete hb;
+    return s;
+  }
+  *out = hb;
+  return SZ_OK;
+}
+
+sz_status sz_batch_create_compress(const sz_cfield* fields, uint32_t n, void* d_ws, uint64_t ws_bytes, sz_batch* out) {
+  return batch_create(fields, nullptr, n, d_ws, ws_bytes, out);
+}
+
+sz_status sz_batch_create_decompress(const sz_dfield* fields, uint32_t n, void* d_ws, uint64_t ws_bytes,
+                                     sz_batch* out) {
+  return batch_create(nullptr, fields, n, d_ws, ws_bytes, out);
+}
+
+sz_status sz_batch_set_geometry(sz_batch b, uint32_t encode_wgs) {
+  g_err.clear();
+  if (!b || encode_wgs == 0) return fail(SZ_EINVAL, "bad batch or geometry");
+  b->geom.encode_wgs = encode_wgs;
+  return SZ_OK;
+}
+
+sz_status sz_batch_run(sz_batch b, hipStream_t stream) {
+  g_err.clear();
+  if (!b) return fail(SZ_EINVAL, "null batch");
+  const hipError_t e = b->decompress ? szx::launch_decompress(b->db, b->block, stream, current_hook())
+                                     : szx::launch_compress(b->cb, b->block, b->geom, stream, current_hook());
+  if (e != hipSuccess) return fail(SZ_EDEVICE, std::string("launch failed: ") + hipGetErrorString(e));
+  return SZ_OK;
+}
+
+void sz_batch_destroy(sz_batch b) { delete b; }
 
 sz_status sz_inspect(const void* h_hdr, uint64_t bytes, sz_params* out, uint64_t* total_bytes) {
   g_err.clear();

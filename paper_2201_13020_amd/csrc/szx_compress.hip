@@ -1,22 +1,25 @@
 // szx_compress.hip -- compression kernels of the SZx method for gfx950.
 //
-// Pipeline of one sz_compress call (all on the caller's stream):
+// Pipeline of one sz_compress call, or of one batch of fields (all on the
+// caller's stream; every pass is one launch over all fields of the batch, a
+// single call being a batch of one, so both run the same code):
 //   k_init      clear counters, tickets and the tile status words of the scans
-//   k_stats     per-block totalOrder min/max (Alg. 1 needs both for mu_k) and,
-//               per workgroup, the finite value range
+//   k_stats     per-block totalOrder min/max (Alg. 1 needs both for mu_k) and
+//               per chunk of tiles the finite value range
 //   k_range     the absolute bound e (for the relative bound: eb times the
-//               global finite range, Sec. III footnote), one workgroup
+//               global finite range, Sec. III footnote), one workgroup a field
 //   k_classify  mid-range mu and constant test of every block (Alg. 1), the
 //               state bits and the mu section; a light single-pass prefix count
 //               of non-constant blocks gives each encode tile its first rank
 //   k_encode    per non-constant block: normalise, keep K bits (eq. (4)), shift
 //               (eq. (5)), verify the bound where it is not proved a priori,
 //               2-bit leading-byte codes and mid bytes. Persistent workgroups
-//               take tiles from interleaved ticket counters; each tile's output
-//               offset comes from a single-pass prefix sum over tiles (Sec. V-B),
+//               take tiles from interleaved ticket counters (float32 tiles of
+//               all fields, then float64 tiles); each tile's output offset comes
+//               from a single-pass prefix sum over its field's tiles (Sec. V-B),
 //               and while a tile waits for it the next tile's data is loaded.
 //               Bytes are packed in LDS and leave in aligned 16-byte stores.
-//   k_finalize  header, section padding, stream size
+//   k_finalize  header, section padding, stream size; one workgroup a field
 #include <algorithm>
 
 #include "szx_device.hpp"
@@ -24,28 +27,18 @@
 
 namespace szx {
 
+// Field of a call, or of a batch entry, as the kernels see it.
+__device__ __forceinline__ const FieldC& field_at(const CBatch& b, uint32_t f) {
+  return b.fields ? b.fields[f] : b.one;
+}
+__device__ __forceinline__ uint32_t field_of(const uint32_t* map, uint64_t t) { return map ? map[t] : 0u; }
+
 // ------------------------------------------------------------------ init ---
 
-__global__ __launch_bounds__(256) void k_init(Counters* ctr, uint32_t* tickets, uint64_t* st1, uint64_t n1,
-                                              uint64_t* st2, uint64_t n2) {
+__global__ __launch_bounds__(256) void k_init(CBatch b) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n1 + n2; i += stride) {
-    if (i < n1)
-      st1[i] = 0;
-    else
-      st2[i - n1] = 0;
-  }
-  if (blockIdx.x == 0) {
-    if (threadIdx.x < kTicketClasses) tickets[threadIdx.x * 64] = 0;
-    if (threadIdx.x == 0) {
-      ctr->err = 0;
-      ctr->klo = ~0ull;
-      ctr->khi = 0;
-      ctr->n_nc = 0;
-      ctr->mid_total = 0;
-      ctr->e_bits = 0;
-    }
-  }
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < b.zero_words; i += stride)
+    b.zero_begin[i] = 0;
 }
 
 // Load EPL consecutive values starting at element i0 (aligned to EPL); values
@@ -101,10 +94,10 @@ __device__ __forceinline__ U group_max(U v) {
 
 // ----------------------------------------------------------------- stats ---
 
-// Per-block totalOrder extrema (as keys) of all values, and per workgroup the
-// finite range (keys; lo > hi when the workgroup saw no finite value) into
-// part[2 * blockIdx.x], part[2 * blockIdx.x + 1]. Two tiles per iteration keep
-// more loads in flight.
+// Per-block totalOrder extrema (as keys) of all values, and per chunk of
+// kStatsChunk tiles the finite range (keys; lo > hi when the chunk saw no
+// finite value) into part[2 * chunk], part[2 * chunk + 1]. A chunk holds tiles
+// of one field; two tiles per iteration keep more loads in flight.
 template <typename T, int B>
 __device__ __forceinline__ void stats_tile(const T (&v)[Geo<T, B>::EPL], int cnt, uint64_t i0, uint64_t nblk,
                                            typename Traits<T>::U* __restrict__ stats,
@@ -133,25 +126,25 @@ __device__ __forceinline__ void stats_tile(const T (&v)[Geo<T, B>::EPL], int cnt
 }
 
 template <typename T, int B>
-__global__ __launch_bounds__(256) void k_stats(const T* __restrict__ x, uint64_t n, uint64_t nblk,
-                                               typename Traits<T>::U* __restrict__ stats,
-                                               uint64_t* __restrict__ part) {
+__device__ __forceinline__ void stats_chunk(const FieldC& f, uint64_t c, uint64_t* s_lo, uint64_t* s_hi) {
   using U = typename Traits<T>::U;
   using G = Geo<T, B>;
   constexpr int EPL = G::EPL;
-  __shared__ U s_lo[kWavesPerWG], s_hi[kWavesPerWG];
+  const T* x = reinterpret_cast<const T*>(f.in);
+  U* stats = reinterpret_cast<U*>(f.stats);
   U flo = (U)~(U)0, fhi = 0;
-  const uint64_t ntile = cdiv(n, (uint64_t)G::TILE);
-  const uint64_t step = gridDim.x;
-  for (uint64_t t = blockIdx.x; t < ntile; t += 2 * step) {
+  const uint64_t ntile = cdiv(f.n, (uint64_t)G::TILE);
+  const uint64_t t0 = c * kStatsChunk;
+  const uint64_t t1 = std::min<uint64_t>(ntile, t0 + kStatsChunk);
+  for (uint64_t t = t0; t < t1; t += 2) {
     const uint64_t i0 = t * G::TILE + (uint64_t)threadIdx.x * EPL;
-    const uint64_t i1 = i0 + step * G::TILE;
-    const bool second = t + step < ntile;
+    const uint64_t i1 = i0 + G::TILE;
+    const bool second = t + 1 < t1;
     T v0[EPL], v1[EPL];
-    const int c0 = load_run<T, EPL>(x, i0, n, v0);
-    const int c1 = second ? load_run<T, EPL>(x, i1, n, v1) : 0;
-    stats_tile<T, B>(v0, c0, i0, nblk, stats, flo, fhi);
-    if (second) stats_tile<T, B>(v1, c1, i1, nblk, stats, flo, fhi);
+    const int c0 = load_run<T, EPL>(x, i0, f.n, v0);
+    const int c1 = second ? load_run<T, EPL>(x, i1, f.n, v1) : 0;
+    stats_tile<T, B>(v0, c0, i0, f.nblk, stats, flo, fhi);
+    if (second) stats_tile<T, B>(v1, c1, i1, f.nblk, stats, flo, fhi);
   }
   flo = group_min<kWave, U>(flo);
   fhi = group_max<kWave, U>(fhi);
@@ -162,31 +155,39 @@ __global__ __launch_bounds__(256) void k_stats(const T* __restrict__ x, uint64_t
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    U lo = s_lo[0], hi = s_hi[0];
+    uint64_t lo = s_lo[0], hi = s_hi[0];
     for (int i = 1; i < kWavesPerWG; ++i) {
       lo = s_lo[i] < lo ? s_lo[i] : lo;
       hi = s_hi[i] > hi ? s_hi[i] : hi;
     }
     // widen to 64 bits keeping "no finite value" as lo > hi
-    part[2 * blockIdx.x] = lo > hi ? ~0ull : (uint64_t)lo;
-    part[2 * blockIdx.x + 1] = lo > hi ? 0ull : (uint64_t)hi;
+    f.part[2 * c] = lo > hi ? ~0ull : lo;
+    f.part[2 * c + 1] = lo > hi ? 0ull : hi;
   }
+}
+
+template <typename T, int B>
+__global__ __launch_bounds__(256) void k_stats(CBatch b) {
+  __shared__ uint64_t s_lo[kWavesPerWG], s_hi[kWavesPerWG];
+  const uint64_t g = blockIdx.x;
+  const FieldC& f = field_at(b, field_of(b.field_stats[Traits<T>::BYTES / 8], g));
+  stats_chunk<T, B>(f, g - f.base_stats, s_lo, s_hi);
 }
 
 // ----------------------------------------------------------------- range ---
 
-// The bound e from the parameters and, for the relative bound, the per-
-// workgroup finite ranges of k_stats. One workgroup.
-template <typename T>
-__global__ __launch_bounds__(256) void k_range(Counters* ctr, const uint64_t* __restrict__ part,
-                                               uint32_t nparts, int rel, double eb) {
+// The bound e of each field from its parameters and, for the relative bound,
+// its chunks' finite ranges. One workgroup a field.
+__global__ __launch_bounds__(256) void k_range(CBatch b) {
   __shared__ uint64_t s_lo[kWavesPerWG], s_hi[kWavesPerWG];
+  const FieldC& f = field_at(b, blockIdx.x);
+  const int rel = f.eb_mode == 1;
   uint64_t lo = ~0ull, hi = 0;
   if (rel) {
-    for (uint32_t i = threadIdx.x; i < nparts; i += kWG) {
-      const uint64_t a = part[2 * i], b = part[2 * i + 1];
+    for (uint32_t i = threadIdx.x; i < f.nparts; i += kWG) {
+      const uint64_t a = f.part[2 * i], c = f.part[2 * i + 1];
       lo = a < lo ? a : lo;
-      hi = b > hi ? b : hi;
+      hi = c > hi ? c : hi;
     }
   }
   lo = group_min<kWave, uint64_t>(lo);
@@ -197,16 +198,14 @@ __global__ __launch_bounds__(256) void k_range(Counters* ctr, const uint64_t* __
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int i = 1; i < kWavesPerWG; ++i) {
+    for (int i = 0; i < kWavesPerWG; ++i) {
       lo = s_lo[i] < lo ? s_lo[i] : lo;
       hi = s_hi[i] > hi ? s_hi[i] : hi;
     }
-    lo = s_lo[0] < lo ? s_lo[0] : lo;
-    hi = s_hi[0] > hi ? s_hi[0] : hi;
-    const T e = bound_from<T>(rel, eb, lo, hi);
-    ctr->klo = lo;
-    ctr->khi = hi;
-    ctr->e_bits = (uint64_t)bits_of(e);
+    f.ctr->klo = lo;
+    f.ctr->khi = hi;
+    f.ctr->e_bits = f.dtype == 0 ? (uint64_t)bits_of(bound_from<float>(rel, f.eb, lo, hi))
+                                 : (uint64_t)bits_of(bound_from<double>(rel, f.eb, lo, hi));
   }
 }
 
@@ -257,22 +256,18 @@ __device__ __forceinline__ BlockPlan<T> plan_block(typename Traits<T>::U kmin, t
 // first non-constant block of every encode tile (a prefix count over tiles of
 // CLS blocks, four per thread at most). The last tile writes n_nc.
 template <typename T, int B>
-__global__ __launch_bounds__(256) void k_classify(const typename Traits<T>::U* __restrict__ stats,
-                                                  uint8_t* __restrict__ out, uint64_t* __restrict__ enc_r0,
-                                                  uint64_t* cls_status, Counters* ctr, uint64_t nblk,
-                                                  uint64_t mu_off) {
+__device__ __forceinline__ void classify_tile(const FieldC& f, uint32_t t, uint32_t* s_scan, uint32_t* s_state,
+                                              uint64_t* s_base) {
   using U = typename Traits<T>::U;
   using G = Geo<T, B>;
   constexpr int TBLK = G::TBLK;
   constexpr int CLS = TBLK > 1024 ? TBLK : 1024;
   constexpr int BPT = CLS / kWG;  // blocks per thread
-  __shared__ uint32_t s_scan[kWavesPerWG];
-  __shared__ uint32_t s_state[CLS / 32];
-  __shared__ uint64_t s_base;
-  const T e = from_bits<T>((U)ctr->e_bits);
+  const U* stats = reinterpret_cast<const U*>(f.stats);
+  const uint64_t nblk = f.nblk;
+  const T e = from_bits<T>((U)f.ctr->e_bits);
   const uint32_t ntiles = (uint32_t)cdiv(nblk, CLS);
-  const uint32_t t = blockIdx.x;
-  T* mus = reinterpret_cast<T*>(out + mu_off);
+  T* mus = reinterpret_cast<T*>(f.out + f.mu_off);
   for (int i = threadIdx.x; i < CLS / 32; i += kWG) s_state[i] = 0;
   __syncthreads();
   const uint64_t k0 = (uint64_t)t * CLS + (uint64_t)threadIdx.x * BPT;
@@ -292,21 +287,32 @@ __global__ __launch_bounds__(256) void k_classify(const typename Traits<T>::U* _
   uint32_t total;
   const uint32_t ex = wg_excl_sum<uint32_t>(cnt, s_scan, total);  // has barriers
   if (threadIdx.x < kWave) {
-    if (threadIdx.x == 0) lookback_publish(cls_status, t, total);
-    const uint64_t p = lookback_resolve(cls_status, t, total, &ctr->err, 1u);
-    if (threadIdx.x == 0) s_base = p;
+    if (threadIdx.x == 0) lookback_publish(f.cls_status, t, total);
+    const uint64_t p = lookback_resolve(f.cls_status, t, total, &f.ctr->err, 1u);
+    if (threadIdx.x == 0) *s_base = p;
   }
   // state bytes of this tile, never past the state section
   const uint64_t state_bytes = (nblk + 7) / 8;
   for (int i = threadIdx.x; i < CLS / 8; i += kWG) {
     const uint64_t byte = (uint64_t)t * (CLS / 8) + i;
-    if (byte < state_bytes) out[96 + byte] = (uint8_t)(s_state[i / 4] >> (8 * (i % 4)));
+    if (byte < state_bytes) f.out[96 + byte] = (uint8_t)(s_state[i / 4] >> (8 * (i % 4)));
   }
   __syncthreads();
-  const uint64_t base = s_base;
+  const uint64_t base = *s_base;
   // first rank of every encode tile that starts in this thread's blocks
-  if ((k0 % TBLK) == 0 && k0 < nblk) enc_r0[k0 / TBLK] = base + ex;
-  if (t == ntiles - 1 && threadIdx.x == 0) ctr->n_nc = base + total;
+  if ((k0 % TBLK) == 0 && k0 < nblk) f.enc_r0[k0 / TBLK] = base + ex;
+  if (t == ntiles - 1 && threadIdx.x == 0) f.ctr->n_nc = base + total;
+}
+
+template <typename T, int B>
+__global__ __launch_bounds__(256) void k_classify(CBatch b) {
+  constexpr int CLS = Geo<T, B>::TBLK > 1024 ? Geo<T, B>::TBLK : 1024;
+  __shared__ uint32_t s_scan[kWavesPerWG];
+  __shared__ uint32_t s_state[CLS / 32 > 32 ? CLS / 32 : 32];
+  __shared__ uint64_t s_base;
+  const uint64_t g = blockIdx.x;
+  const FieldC& f = field_at(b, field_of(b.field_cls[Traits<T>::BYTES / 8], g));
+  classify_tile<T, B>(f, (uint32_t)(g - f.base_cls), s_scan, s_state, &s_base);
 }
 
 // ---------------------------------------------------------------- encode ---
@@ -422,6 +428,8 @@ struct TileIn {
   int cnt[Geo<T, B>::SUB];
   uint32_t rank[Geo<T, B>::SUB];  // rank of the row's block among the tile's non-constant ones
   uint64_t r0;                    // rank of the tile's first non-constant block
+  uint32_t field;                 // batch entry
+  uint32_t tile;                  // tile within the field
 };
 
 // Loads and plans tile t: extrema, plan, ranks within the tile (barriers),
@@ -459,46 +467,56 @@ __device__ __forceinline__ void tile_load(TileIn<T, B>& in, uint32_t t, const T*
   for (int s = 0; s < SUB; ++s) in.rank[s] = __shfl(in.rank[s], lane - lig);
 }
 
+// The encode pass for the tiles of element type T: persistent workgroups take
+// tickets from the kTicketClasses counters of this type; ticket i of class c
+// is global tile kTicketClasses * i + c, global tiles running over the fields
+// of this type in order.
 template <typename T, int B>
-__global__ __launch_bounds__(256) void k_encode(const T* __restrict__ x, uint8_t* __restrict__ out,
-                                                const typename Traits<T>::U* __restrict__ stats,
-                                                const uint64_t* __restrict__ enc_r0, uint64_t* mid_status,
-                                                uint32_t* tickets, Counters* ctr, uint64_t n, uint64_t nblk,
-                                                uint64_t mu_off) {
+__device__ __forceinline__ void encode_pass(const CBatch& b, uint32_t* s_scan, uint32_t* s_tile, uint64_t* s_base,
+                                            uint32_t* s_stage) {
   using U = typename Traits<T>::U;
   using G = Geo<T, B>;
   constexpr int EPL = G::EPL, LPB = G::LPB, SUB = G::SUB;
   constexpr int BYTES = Traits<T>::BYTES;
   constexpr int STAGE_WORDS = (G::TILE * SUB * BYTES + 16) / 4 + 8;
-  __shared__ uint32_t s_scan[SUB * kWavesPerWG];
-  __shared__ uint32_t s_tile;
-  __shared__ uint64_t s_base;
-  __shared__ __align__(16) uint32_t s_stage[STAGE_WORDS];
-
-  const uint64_t n_nc = ctr->n_nc;
-  const T e = from_bits<T>((U)ctr->e_bits);
-  const Sections sec = sections(nblk, n_nc, BYTES, B, 0);
-  const uint32_t ntiles = (uint32_t)cdiv(nblk, G::TBLK);
+  constexpr int DT = sizeof(T) == 4 ? 0 : 1;
+  const uint64_t ntiles = b.tiles_enc[DT];
+  if (ntiles == 0) return;
   const uint32_t cls = blockIdx.x % kTicketClasses;
-  T* mus = reinterpret_cast<T*>(out + mu_off);
+  uint32_t* ticket = b.tickets + (DT * kTicketClasses + cls) * 64;
   const int lig = threadIdx.x % LPB;
 
-  auto claim = [&]() -> uint32_t {
-    if (threadIdx.x == 0) s_tile = atomicAdd(tickets + cls * 64, 1u) * kTicketClasses + cls;
+  auto claim = [&]() -> uint64_t {
+    if (threadIdx.x == 0) *s_tile = atomicAdd(ticket, 1u);
     __syncthreads();
-    const uint32_t v = s_tile;
+    const uint64_t v = (uint64_t)*s_tile * kTicketClasses + cls;
     __syncthreads();
     return v;
+  };
+  auto load = [&](TileIn<T, B>& in, uint64_t gt) {
+    const uint32_t fi = field_of(b.field_enc[DT], gt);
+    const FieldC& f = field_at(b, fi);
+    in.field = fi;
+    in.tile = (uint32_t)(gt - f.base_enc);
+    tile_load<T, B>(in, in.tile, reinterpret_cast<const T*>(f.in), reinterpret_cast<const U*>(f.stats), f.enc_r0,
+                    f.n, f.nblk, from_bits<T>((U)f.ctr->e_bits), s_scan);
   };
 
   for (int i = threadIdx.x; i < STAGE_WORDS / 4; i += kWG)
     reinterpret_cast<uint4*>(s_stage)[i] = make_uint4(0, 0, 0, 0);
-  uint32_t t = claim();
-  if (t >= ntiles) return;
+  uint64_t gt = claim();
+  if (gt >= ntiles) return;
   TileIn<T, B> cur;
-  tile_load<T, B>(cur, t, x, stats, enc_r0, n, nblk, e, s_scan);
+  load(cur, gt);
 
   for (;;) {
+    const FieldC& f = field_at(b, cur.field);
+    const uint32_t t = cur.tile;
+    const T e = from_bits<T>((U)f.ctr->e_bits);
+    const Sections sec = sections(f.nblk, f.ctr->n_nc, BYTES, B, 0);
+    uint8_t* out = f.out;
+    T* mus = reinterpret_cast<T*>(out + f.mu_off);
+    uint64_t* mid_status = f.enc_mid;
     // Row by row: encode with error control (K0, then one more mantissa bit,
     // then raw; every lane votes, lanes without a coded block vote yes), codes
     // and byte counts, the row's offsets, K bytes and codes, and the staged
@@ -569,19 +587,22 @@ __global__ __launch_bounds__(256) void k_encode(const T* __restrict__ x, uint8_t
     }
     if (threadIdx.x == 0) lookback_publish(mid_status, t, tile_bytes);
     const uint32_t t_cur = t;
+    const uint32_t f_cur = cur.field;
 
     // the next tile's loads go out while this tile's offset is resolved
-    t = claim();  // its barriers also order the staging before the copy-out
-    const bool more = t < ntiles;
-    if (more) tile_load<T, B>(cur, t, x, stats, enc_r0, n, nblk, e, s_scan);
+    gt = claim();  // its barriers also order the staging before the copy-out
+    const bool more = gt < ntiles;
+    if (more) load(cur, gt);
+    const FieldC& fc = field_at(b, f_cur);
     if (threadIdx.x < kWave) {
-      const uint64_t p = lookback_resolve(mid_status, t_cur, tile_bytes, &ctr->err, 1u);
-      if (threadIdx.x == 0) s_base = p;
+      const uint64_t p = lookback_resolve(fc.enc_mid, t_cur, tile_bytes, &fc.ctr->err, 1u);
+      if (threadIdx.x == 0) *s_base = p;
     }
     __syncthreads();
-    const uint64_t base = s_base;
-    copy_out(out, sec.mid + base, s_stage, tile_bytes);
-    if (t_cur == ntiles - 1 && threadIdx.x == 0) ctr->mid_total = base + tile_bytes;
+    const uint64_t base = *s_base;
+    const Sections secc = sections(fc.nblk, fc.ctr->n_nc, BYTES, B, 0);
+    copy_out(fc.out, secc.mid + base, s_stage, tile_bytes);
+    if (t_cur == cdiv(fc.nblk, G::TBLK) - 1 && threadIdx.x == 0) fc.ctr->mid_total = base + tile_bytes;
     __syncthreads();
     for (int i = threadIdx.x; i < STAGE_WORDS / 4; i += kWG)
       reinterpret_cast<uint4*>(s_stage)[i] = make_uint4(0, 0, 0, 0);
@@ -589,123 +610,94 @@ __global__ __launch_bounds__(256) void k_encode(const T* __restrict__ x, uint8_t
   }
 }
 
+template <typename T, int B>
+__global__ __launch_bounds__(256) void k_encode(CBatch b) {
+  using G = Geo<T, B>;
+  __shared__ uint32_t s_scan[G::SUB * kWavesPerWG];
+  __shared__ uint32_t s_tile;
+  __shared__ uint64_t s_base;
+  __shared__ __align__(16) uint32_t s_stage[(G::TILE * G::SUB * Traits<T>::BYTES + 16) / 4 + 8];
+  encode_pass<T, B>(b, s_scan, &s_tile, &s_base, s_stage);
+}
+
 // --------------------------------------------------------------- finalize ---
 
-struct HeaderArgs {
-  uint32_t dtype, eb_mode, ndims, b;
-  uint64_t dims[4];
-  uint64_t n, nblk;
-  double eb;
-  uint32_t w;
-};
-
-__global__ void k_finalize(uint8_t* __restrict__ out, uint64_t* out_size, const Counters* ctr,
-                           HeaderArgs h) {
+// Header, section padding and stream size; one workgroup a field.
+__global__ void k_finalize(CBatch b) {
+  const FieldC& f = field_at(b, blockIdx.x);
+  const Counters* ctr = f.ctr;
+  const uint32_t w = f.dtype == 0 ? 4 : 8;
   const uint64_t n_nc = ctr->n_nc, mid_total = ctr->mid_total;
-  const Sections s = sections(h.nblk, n_nc, h.w, h.b, mid_total);
+  const Sections s = sections(f.nblk, n_nc, w, f.b, mid_total);
+  uint8_t* out = f.out;
   if (threadIdx.x == 0) {
     uint32_t* o32 = reinterpret_cast<uint32_t*>(out);
     uint64_t* o64 = reinterpret_cast<uint64_t*>(out);
     o32[0] = kMagic;
-    o32[1] = (uint32_t)kVersion | (h.dtype << 8) | (h.eb_mode << 16) | (h.ndims << 24);
-    o32[2] = h.b;
+    o32[1] = (uint32_t)kVersion | (f.dtype << 8) | (f.eb_mode << 16) | (f.ndims << 24);
+    o32[2] = f.b;
     o32[3] = 0;
-    for (int d = 0; d < 4; ++d) o64[2 + d] = h.dims[d];
-    o64[6] = h.n;
-    o64[7] = (uint64_t)__double_as_longlong(h.eb);
+    for (int d = 0; d < 4; ++d) o64[2 + d] = f.dims[d];
+    o64[6] = f.n;
+    o64[7] = (uint64_t)__double_as_longlong(f.eb);
     o64[8] = ctr->e_bits;
-    o64[9] = h.nblk;
+    o64[9] = f.nblk;
     o64[10] = n_nc;
     o64[11] = mid_total;
-    *out_size = ctr->err ? 0 : s.total;
+    *f.out_size = ctr->err ? 0 : s.total;
   }
-  // zero padding: after the state words, after mu, after K, after codes
-  const uint64_t pads[4][2] = {{96 + cdiv(h.nblk, 8), s.mu},
-                               {s.mu + h.nblk * h.w, s.kbytes},
+  // zero padding: after the state bits, after mu, after K, after codes
+  const uint64_t pads[4][2] = {{96 + cdiv(f.nblk, 8), s.mu},
+                               {s.mu + f.nblk * w, s.kbytes},
                                {s.kbytes + n_nc, s.codes},
-                               {s.codes + n_nc * (h.b / 4), s.mid}};
+                               {s.codes + n_nc * (f.b / 4), s.mid}};
   for (int p = 0; p < 4; ++p)
     for (uint64_t i = pads[p][0] + threadIdx.x; i < pads[p][1]; i += blockDim.x) out[i] = 0;
 }
 
 // ---------------------------------------------------------------- launch ---
 
-template <typename T, int B>
-hipError_t launch_compress_t(const Job& j, const CompressLaunch& L, TimerHook hook) {
-  using U = typename Traits<T>::U;
-  using G = Geo<T, B>;
-  constexpr uint32_t CLS = G::TBLK > 1024 ? G::TBLK : 1024;
-  const WsLayout W = ws_layout(j.nblk, j.w, j.b);
-  Counters* ctr = reinterpret_cast<Counters*>(L.ws + W.counters);
-  uint32_t* tickets = reinterpret_cast<uint32_t*>(L.ws + W.tickets);
-  U* stats = reinterpret_cast<U*>(L.ws + W.stats);
-  uint64_t* part = reinterpret_cast<uint64_t*>(L.ws + W.range_part);
-  uint64_t* enc_r0 = reinterpret_cast<uint64_t*>(L.ws + W.enc_r0);
-  uint64_t* cls_st = reinterpret_cast<uint64_t*>(L.ws + W.cls_status);
-  uint64_t* enc_mid = reinterpret_cast<uint64_t*>(L.ws + W.enc_mid);
-  const uint64_t ncls = cdiv(j.nblk, CLS);
-  const uint64_t nenc = cdiv(j.nblk, G::TBLK);
-  const Sections sec0 = sections(j.nblk, 0, j.w, j.b, 0);
-
+template <int B>
+hipError_t launch_compress_b(const CBatch& b, const CLaunchGeom& g, hipStream_t stream, TimerHook hook) {
   auto run = [&](const char* name, auto&& fn) {
-    if (hook) hook(name, L.stream, 1);
+    if (hook) hook(name, stream, 1);
     fn();
-    if (hook) hook(name, L.stream, 0);
+    if (hook) hook(name, stream, 0);
   };
-  {
-    const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(cdiv(ncls + nenc, 256), 1024));
-    run("k_init", [&] { k_init<<<grid, 256, 0, L.stream>>>(ctr, tickets, cls_st, ncls, enc_mid, nenc); });
+  const uint32_t gi = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(cdiv(b.zero_words, 256), 1024));
+  run("k_init", [&] { k_init<<<gi, 256, 0, stream>>>(b); });
+  if (b.tiles_stats[0] + b.tiles_stats[1] > 0) {
+    if (b.tiles_stats[0]) run("k_stats", [&] { k_stats<float, B><<<(uint32_t)b.tiles_stats[0], 256, 0, stream>>>(b); });
+    if (b.tiles_stats[1]) run("k_stats", [&] { k_stats<double, B><<<(uint32_t)b.tiles_stats[1], 256, 0, stream>>>(b); });
+    run("k_range", [&] { k_range<<<b.nfields, 256, 0, stream>>>(b); });
+    if (b.tiles_cls[0]) run("k_classify", [&] { k_classify<float, B><<<(uint32_t)b.tiles_cls[0], 256, 0, stream>>>(b); });
+    if (b.tiles_cls[1]) run("k_classify", [&] { k_classify<double, B><<<(uint32_t)b.tiles_cls[1], 256, 0, stream>>>(b); });
+    for (int dt = 0; dt < 2; ++dt) {
+      if (!b.tiles_enc[dt]) continue;
+      const uint32_t genc = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(b.tiles_enc[dt], g.encode_wgs));
+      if (dt == 0)
+        run("k_encode", [&] { k_encode<float, B><<<genc, 256, 0, stream>>>(b); });
+      else
+        run("k_encode", [&] { k_encode<double, B><<<genc, 256, 0, stream>>>(b); });
+    }
   }
-  if (j.nblk > 0) {
-    const uint64_t ntile = cdiv(j.n, (uint64_t)G::TILE);
-    const uint32_t grid = (uint32_t)std::min<uint64_t>(ntile, std::min<uint64_t>(kMaxRangeParts, (uint64_t)L.n_cu * 4));
-    run("k_stats", [&] {
-      k_stats<T, B><<<grid, 256, 0, L.stream>>>((const T*)L.in, j.n, j.nblk, stats, part);
-    });
-    run("k_range", [&] {
-      k_range<T><<<1, 256, 0, L.stream>>>(ctr, part, grid, j.eb_mode == 1 ? 1 : 0, j.eb);
-    });
-    run("k_classify", [&] {
-      k_classify<T, B><<<(uint32_t)ncls, 256, 0, L.stream>>>(stats, L.out, enc_r0, cls_st, ctr, j.nblk, sec0.mu);
-    });
-    // persistent: a few workgroups per CU, at least one per ticket class
-    const uint32_t genc = (uint32_t)std::min<uint64_t>(nenc, (uint64_t)L.n_cu * 4);
-    run("k_encode", [&] {
-      k_encode<T, B><<<genc, 256, 0, L.stream>>>((const T*)L.in, L.out, stats, enc_r0, enc_mid, tickets, ctr,
-                                                  j.n, j.nblk, sec0.mu);
-    });
-  }
-  HeaderArgs h;
-  h.dtype = j.dtype;
-  h.eb_mode = j.eb_mode;
-  h.ndims = j.ndims;
-  h.b = j.b;
-  for (int d = 0; d < 4; ++d) h.dims[d] = j.dims[d];
-  h.n = j.n;
-  h.nblk = j.nblk;
-  h.eb = j.eb;
-  h.w = j.w;
-  run("k_finalize", [&] { k_finalize<<<1, 64, 0, L.stream>>>(L.out, L.out_size, ctr, h); });
+  run("k_finalize", [&] { k_finalize<<<b.nfields, 64, 0, stream>>>(b); });
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_compress_dt(const Job& j, const CompressLaunch& L, TimerHook hook) {
-  switch (j.b) {
-    case 8: return launch_compress_t<T, 8>(j, L, hook);
-    case 16: return launch_compress_t<T, 16>(j, L, hook);
-    case 32: return launch_compress_t<T, 32>(j, L, hook);
-    case 64: return launch_compress_t<T, 64>(j, L, hook);
-    case 128: return launch_compress_t<T, 128>(j, L, hook);
-    case 256: return launch_compress_t<T, 256>(j, L, hook);
-    case 512: return launch_compress_t<T, 512>(j, L, hook);
-    case 1024: return launch_compress_t<T, 1024>(j, L, hook);
+hipError_t launch_compress(const CBatch& b, uint32_t block, const CLaunchGeom& g, hipStream_t stream,
+                           TimerHook hook) {
+  switch (block) {
+    case 8: return launch_compress_b<8>(b, g, stream, hook);
+    case 16: return launch_compress_b<16>(b, g, stream, hook);
+    case 32: return launch_compress_b<32>(b, g, stream, hook);
+    case 64: return launch_compress_b<64>(b, g, stream, hook);
+    case 128: return launch_compress_b<128>(b, g, stream, hook);
+    case 256: return launch_compress_b<256>(b, g, stream, hook);
+    case 512: return launch_compress_b<512>(b, g, stream, hook);
+    case 1024: return launch_compress_b<1024>(b, g, stream, hook);
     default: return hipErrorInvalidValue;
   }
-}
-
-hipError_t launch_compress(const Job& j, const CompressLaunch& L, TimerHook hook) {
-  return j.dtype == 0 ? launch_compress_dt<float>(j, L, hook) : launch_compress_dt<double>(j, L, hook);
 }
 
 }  // namespace szx

@@ -28,23 +28,17 @@ namespace szx {
 constexpr uint32_t kStatusCorrupt = 3;  // SZ_ECORRUPT
 constexpr uint32_t kStatusDevice = 4;   // SZ_EDEVICE: a bounded wait gave up
 
-struct DecodeArgs {
-  const uint8_t* in;
-  uint64_t in_bytes;
-  uint8_t* out;
-  uint32_t* status;
-  uint64_t* index;  // per decode tile: first rank, first mid byte
-  uint64_t* rank_st;
-  uint64_t* mid_st;
-  uint64_t n, nblk;
-  uint32_t dtype, ndims;
-  uint64_t dims[4];
-};
+__device__ __forceinline__ const FieldD& field_at(const DBatch& b, uint32_t f) {
+  return b.fields ? b.fields[f] : b.one;
+}
+__device__ __forceinline__ uint32_t dfield_of(const uint32_t* map, uint64_t t) { return map ? map[t] : 0u; }
 
-__global__ __launch_bounds__(256) void k_dinit(uint64_t* st1, uint64_t n1, uint32_t* status) {
+__global__ __launch_bounds__(256) void k_dinit(DBatch b) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n1; i += stride) st1[i] = 0;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *status = 0;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < b.zero_words; i += stride)
+    b.zero_begin[i] = 0;
+  const uint64_t nf = b.fields ? b.nfields : 1;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nf; i += stride) *field_at(b, (uint32_t)i).status = 0;
 }
 
 __device__ __forceinline__ uint64_t rd64(const uint8_t* p) { return *reinterpret_cast<const uint64_t*>(p); }
@@ -140,7 +134,7 @@ struct StreamInfo {
 };
 
 template <int BYTES, int B>
-__device__ __forceinline__ StreamInfo read_header(const DecodeArgs& a) {
+__device__ __forceinline__ StreamInfo read_header(const FieldD& a) {
   StreamInfo h;
   const uint8_t* in = a.in;
   h.ok = a.in_bytes >= kHeaderBytes;
@@ -203,21 +197,21 @@ __device__ __forceinline__ uint32_t block_mid_bytes(const uint8_t* cp, uint32_t 
 // and mid bytes, each through a light single-pass prefix sum; writes the first
 // rank and first mid byte of every decode tile in it.
 template <typename T, int B>
-__global__ __launch_bounds__(256) void k_dindex(DecodeArgs a) {
+__device__ __forceinline__ void dindex_tile(const FieldD& a, uint32_t t, uint32_t* s_scan, uint64_t* s_r0p,
+                                            uint64_t* s_m0p) {
   using G = Geo<T, B>;
   constexpr int BYTES = Traits<T>::BYTES;
   constexpr int TBLK = G::TBLK;
   constexpr int CLS = TBLK > 1024 ? TBLK : 1024;
   constexpr int BPT = CLS / kWG;
-  __shared__ uint32_t s_scan[kWavesPerWG];
-  __shared__ uint64_t s_r0, s_m0;
+  uint64_t& s_r0 = *s_r0p;
+  uint64_t& s_m0 = *s_m0p;
   const StreamInfo h = read_header<BYTES, B>(a);
   if (!h.ok) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) atomicMax(a.status, kStatusCorrupt);
+    if (t == 0 && threadIdx.x == 0) atomicMax(a.status, kStatusCorrupt);
     return;
   }
   const uint32_t ntiles = (uint32_t)cdiv(a.nblk, CLS);
-  const uint32_t t = blockIdx.x;
   const uint8_t* in = a.in;
   const uint64_t k0 = (uint64_t)t * CLS + (uint64_t)threadIdx.x * BPT;
   bool bad = false;
@@ -276,19 +270,25 @@ __global__ __launch_bounds__(256) void k_dindex(DecodeArgs a) {
 }
 
 template <typename T, int B>
-__global__ __launch_bounds__(256) void k_decode(DecodeArgs a) {
+__global__ __launch_bounds__(256) void k_dindex(DBatch b) {
+  __shared__ uint32_t s_scan[kWavesPerWG];
+  __shared__ uint64_t s_r0, s_m0;
+  const uint64_t g = blockIdx.x;
+  const FieldD& f = field_at(b, dfield_of(b.field_idx[Traits<T>::BYTES / 8], g));
+  dindex_tile<T, B>(f, (uint32_t)(g - f.base_idx), s_scan, &s_r0, &s_m0);
+}
+
+template <typename T, int B>
+__device__ __forceinline__ void decode_tile(const FieldD& a, uint32_t t, uint32_t* s_scan, uint32_t* s_stage) {
   using U = typename Traits<T>::U;
   using G = Geo<T, B>;
   constexpr int EPL = G::EPL, LPB = G::LPB, TB = G::TB, SUB = G::SUB, TBLK = G::TBLK;
   constexpr int BYTES = Traits<T>::BYTES;
   constexpr int STAGE_WORDS = (G::TILE * SUB * BYTES + 32) / 4 + 8;
-  __shared__ uint32_t s_scan[SUB * kWavesPerWG];
-  __shared__ __align__(16) uint32_t s_stage[STAGE_WORDS];
 
   const StreamInfo h = read_header<BYTES, B>(a);
   if (!h.ok) return;  // k_dindex reported it
   const uint32_t ntiles = (uint32_t)cdiv(a.nblk, TBLK);
-  const uint32_t t = blockIdx.x;
   if (t >= ntiles) return;
   const uint8_t* in = a.in;
   const int g = threadIdx.x / LPB, lig = threadIdx.x % LPB;
@@ -451,64 +451,46 @@ __global__ __launch_bounds__(256) void k_decode(DecodeArgs a) {
   if (__ballot(bad) != 0 && lane == 0) atomicMax(a.status, kStatusCorrupt);
 }
 
+template <typename T, int B>
+__global__ __launch_bounds__(256) void k_decode(DBatch b) {
+  using G = Geo<T, B>;
+  __shared__ uint32_t s_scan[G::SUB * kWavesPerWG];
+  __shared__ __align__(16) uint32_t s_stage[(G::TILE * G::SUB * Traits<T>::BYTES + 32) / 4 + 8];
+  const uint64_t g = blockIdx.x;
+  const FieldD& f = field_at(b, dfield_of(b.field_dec[Traits<T>::BYTES / 8], g));
+  decode_tile<T, B>(f, (uint32_t)(g - f.base_dec), s_scan, s_stage);
+}
+
 // ---------------------------------------------------------------- launch ---
 
-template <typename T, int B>
-hipError_t launch_decompress_t(const Job& j, const DecompressLaunch& L, TimerHook hook) {
-  using G = Geo<T, B>;
-  constexpr uint32_t CLS = G::TBLK > 1024 ? G::TBLK : 1024;
-  const WsLayout W = ws_layout(j.nblk, j.w, j.b);
-  const uint64_t ncls = cdiv(j.nblk, CLS);
-  const uint64_t ntile = cdiv(j.nblk, G::TBLK);
-  uint64_t* rank_st = reinterpret_cast<uint64_t*>(L.ws + W.dec_rank);
-  // dec_rank and dec_mid are adjacent pieces of the workspace: clear both
-  const uint64_t nclear = (W.dec_mid - W.dec_rank) / 8 + ncls;
+template <int B>
+hipError_t launch_decompress_b(const DBatch& b, hipStream_t stream, TimerHook hook) {
   auto run = [&](const char* name, auto&& fn) {
-    if (hook) hook(name, L.stream, 1);
+    if (hook) hook(name, stream, 1);
     fn();
-    if (hook) hook(name, L.stream, 0);
+    if (hook) hook(name, stream, 0);
   };
-  {
-    const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(cdiv(nclear, 256), 1024));
-    run("k_dinit", [&] { k_dinit<<<grid, 256, 0, L.stream>>>(rank_st, nclear, L.status); });
-  }
-  DecodeArgs a;
-  a.in = (const uint8_t*)L.in;
-  a.in_bytes = L.in_bytes;
-  a.out = (uint8_t*)L.out;
-  a.status = L.status;
-  a.index = reinterpret_cast<uint64_t*>(L.ws + W.dec_index);
-  a.rank_st = rank_st;
-  a.mid_st = reinterpret_cast<uint64_t*>(L.ws + W.dec_mid);
-  a.n = j.n;
-  a.nblk = j.nblk;
-  a.dtype = j.dtype;
-  a.ndims = j.ndims;
-  for (int d = 0; d < 4; ++d) a.dims[d] = j.dims[d];
-  const uint32_t gi = (uint32_t)std::max<uint64_t>(1, ncls);
-  run("k_dindex", [&] { k_dindex<T, B><<<gi, 256, 0, L.stream>>>(a); });
-  const uint32_t gd = (uint32_t)std::max<uint64_t>(1, ntile);
-  run("k_decode", [&] { k_decode<T, B><<<gd, 256, 0, L.stream>>>(a); });
+  const uint32_t gi = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(cdiv(b.zero_words, 256), 1024));
+  run("k_dinit", [&] { k_dinit<<<gi, 256, 0, stream>>>(b); });
+  if (b.tiles_idx[0]) run("k_dindex", [&] { k_dindex<float, B><<<(uint32_t)b.tiles_idx[0], 256, 0, stream>>>(b); });
+  if (b.tiles_idx[1]) run("k_dindex", [&] { k_dindex<double, B><<<(uint32_t)b.tiles_idx[1], 256, 0, stream>>>(b); });
+  if (b.tiles_dec[0]) run("k_decode", [&] { k_decode<float, B><<<(uint32_t)b.tiles_dec[0], 256, 0, stream>>>(b); });
+  if (b.tiles_dec[1]) run("k_decode", [&] { k_decode<double, B><<<(uint32_t)b.tiles_dec[1], 256, 0, stream>>>(b); });
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_decompress_dt(const Job& j, const DecompressLaunch& L, TimerHook hook) {
-  switch (j.b) {
-    case 8: return launch_decompress_t<T, 8>(j, L, hook);
-    case 16: return launch_decompress_t<T, 16>(j, L, hook);
-    case 32: return launch_decompress_t<T, 32>(j, L, hook);
-    case 64: return launch_decompress_t<T, 64>(j, L, hook);
-    case 128: return launch_decompress_t<T, 128>(j, L, hook);
-    case 256: return launch_decompress_t<T, 256>(j, L, hook);
-    case 512: return launch_decompress_t<T, 512>(j, L, hook);
-    case 1024: return launch_decompress_t<T, 1024>(j, L, hook);
+hipError_t launch_decompress(const DBatch& b, uint32_t block, hipStream_t stream, TimerHook hook) {
+  switch (block) {
+    case 8: return launch_decompress_b<8>(b, stream, hook);
+    case 16: return launch_decompress_b<16>(b, stream, hook);
+    case 32: return launch_decompress_b<32>(b, stream, hook);
+    case 64: return launch_decompress_b<64>(b, stream, hook);
+    case 128: return launch_decompress_b<128>(b, stream, hook);
+    case 256: return launch_decompress_b<256>(b, stream, hook);
+    case 512: return launch_decompress_b<512>(b, stream, hook);
+    case 1024: return launch_decompress_b<1024>(b, stream, hook);
     default: return hipErrorInvalidValue;
   }
-}
-
-hipError_t launch_decompress(const Job& j, const DecompressLaunch& L, TimerHook hook) {
-  return j.dtype == 0 ? launch_decompress_dt<float>(j, L, hook) : launch_decompress_dt<double>(j, L, hook);
 }
 
 }  // namespace szx

@@ -66,32 +66,51 @@ __host__ __device__ inline uint32_t cls_blocks(uint32_t b, uint32_t w) {
   return t > 1024 ? t : 1024;
 }
 
-// Most workgroups of the extrema pass; each leaves its finite range here.
-constexpr uint32_t kMaxRangeParts = 4096;
-// Ticket classes of the persistent encode pass.
+// Ticket classes of the persistent encode pass (per element type).
 constexpr uint32_t kTicketClasses = 8;
+// Tiles of the extrema pass per chunk; a chunk leaves one finite range.
+constexpr uint32_t kStatsChunk = 8;
 
-// Workspace carve-up; every piece 256-byte aligned.
-struct WsLayout {
-  uint64_t counters, tickets, range_part, stats, enc_r0, cls_status, enc_mid, dec_index, dec_rank, dec_mid, total;
-  uint64_t ntile, ncls;
+// Values per row of a tile for block size b (mirrors Geo::TILE).
+__host__ __device__ inline uint64_t row_values(uint32_t b) { return 256ull * (b >= 512 ? b / 64 : 8); }
+
+// Per-field sizes of the passes.
+struct FieldTiles {
+  uint64_t chunks;  // extrema pass
+  uint64_t cls;     // classification / decoder index tiles
+  uint64_t enc;     // encode / decode tiles
 };
 
-__host__ __device__ inline WsLayout ws_layout(uint64_t nblk, uint32_t w, uint32_t b) {
+__host__ __device__ inline FieldTiles field_tiles(uint64_t n, uint64_t nblk, uint32_t w, uint32_t b) {
+  FieldTiles t;
+  t.chunks = cdiv(cdiv(n, row_values(b)), kStatsChunk);
+  t.cls = cdiv(nblk, cls_blocks(b, w));
+  t.enc = cdiv(nblk, tile_blocks(b, w));
+  return t;
+}
+
+// Workspace of one field: a cleared region first (counters, tickets, scan
+// status words), then the rest; every piece 256-byte aligned.
+struct WsLayout {
+  uint64_t counters, tickets, cls_status, enc_mid, dec_rank, dec_mid, zero_end;
+  uint64_t part, stats, enc_r0, dec_index, total;
+};
+
+__host__ __device__ inline WsLayout ws_layout(uint64_t n, uint64_t nblk, uint32_t w, uint32_t b) {
+  const FieldTiles ft = field_tiles(n, nblk, w, b);
   WsLayout L;
-  L.ntile = cdiv(nblk, tile_blocks(b, w)) + 1;
-  L.ncls = cdiv(nblk, cls_blocks(b, w)) + 1;
   L.counters = 0;
   L.tickets = 256;
-  L.range_part = align256(L.tickets + (uint64_t)kTicketClasses * 256);
-  L.stats = align256(L.range_part + (uint64_t)kMaxRangeParts * 16);
+  L.cls_status = align256(L.tickets + 2ull * kTicketClasses * 256);
+  L.enc_mid = align256(L.cls_status + (ft.cls + 1) * 8);
+  L.dec_rank = align256(L.enc_mid + (ft.enc + 1) * 8);
+  L.dec_mid = align256(L.dec_rank + (ft.cls + 1) * 8);
+  L.zero_end = align256(L.dec_mid + (ft.cls + 1) * 8);
+  L.part = L.zero_end;
+  L.stats = align256(L.part + (ft.chunks + 1) * 16);
   L.enc_r0 = align256(L.stats + nblk * 2 * (uint64_t)w);
-  L.cls_status = align256(L.enc_r0 + L.ntile * 8);
-  L.enc_mid = align256(L.cls_status + L.ncls * 8);
-  L.dec_index = align256(L.enc_mid + L.ntile * 8);
-  L.dec_rank = align256(L.dec_index + L.ntile * 16);
-  L.dec_mid = align256(L.dec_rank + L.ncls * 8);
-  L.total = align256(L.dec_mid + L.ncls * 8);
+  L.dec_index = align256(L.enc_r0 + (ft.enc + 1) * 8);
+  L.total = align256(L.dec_index + (ft.enc + 1) * 16);
   return L;
 }
 

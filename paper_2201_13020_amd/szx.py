@@ -30,6 +30,16 @@ class SzParams(ctypes.Structure):
     ]
 
 
+class SzCField(ctypes.Structure):
+    _fields_ = [("params", SzParams), ("d_in", ctypes.c_void_p), ("d_out", ctypes.c_void_p),
+                ("out_cap", ctypes.c_uint64), ("d_out_size", ctypes.c_void_p)]
+
+
+class SzDField(ctypes.Structure):
+    _fields_ = [("expected", SzParams), ("d_in", ctypes.c_void_p), ("in_bytes", ctypes.c_uint64),
+                ("d_out", ctypes.c_void_p), ("out_cap", ctypes.c_uint64), ("d_status", ctypes.c_void_p)]
+
+
 class SzError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"{STATUS.get(code, code)}: {msg}")
@@ -65,6 +75,19 @@ def lib():
         L.sz_timing_read.argtypes = [ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_uint32), ctypes.c_uint32]
         L.sz_timing_read.restype = ctypes.c_uint32
+        CF, DF = ctypes.POINTER(SzCField), ctypes.POINTER(SzDField)
+        L.sz_batch_workspace_size.argtypes = [CF, DF, ctypes.c_uint32]
+        L.sz_batch_workspace_size.restype = u64
+        L.sz_batch_create_compress.argtypes = [CF, ctypes.c_uint32, vp, u64, ctypes.POINTER(vp)]
+        L.sz_batch_create_compress.restype = ctypes.c_int
+        L.sz_batch_create_decompress.argtypes = [DF, ctypes.c_uint32, vp, u64, ctypes.POINTER(vp)]
+        L.sz_batch_create_decompress.restype = ctypes.c_int
+        L.sz_batch_set_geometry.argtypes = [vp, ctypes.c_uint32]
+        L.sz_batch_set_geometry.restype = ctypes.c_int
+        L.sz_batch_run.argtypes = [vp, vp]
+        L.sz_batch_run.restype = ctypes.c_int
+        L.sz_batch_destroy.argtypes = [vp]
+        L.sz_batch_destroy.restype = None
         _lib = L
     return _lib
 
@@ -205,3 +228,105 @@ def to_host_stream(out, out_size):
     """Synchronise and return the compressed stream as bytes."""
     n = int(out_size.cpu().view(torch.int64).item())
     return out[:n].cpu().numpy().tobytes()
+
+
+class Batch:
+    """A planned batch: its descriptor table lives in `ws`; run() enqueues the
+    passes over all fields (one launch per pass). Keeps the tensors it names
+    alive for its own lifetime."""
+
+    def __init__(self, handle, ws, keep, outs=None, sizes=None, statuses=None):
+        self._h = handle
+        self.ws = ws
+        self._keep = keep
+        self.outs = outs
+        self.sizes = sizes
+        self.statuses = statuses
+
+    def run(self, stream=None):
+        _check(lib().sz_batch_run(self._h, _stream_handle(stream)), "sz_batch_run")
+
+    def set_geometry(self, encode_wgs):
+        _check(lib().sz_batch_set_geometry(self._h, int(encode_wgs)), "sz_batch_set_geometry")
+
+    def close(self):
+        if self._h:
+            lib().sz_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def compress_batch(xs, ebs, modes="rel", block=128, dims=None, outs=None, sizes=None, ws=None):
+    """Plan a compression batch over the device tensors xs (mixed float32 and
+    float64 allowed; one block size). Returns a Batch whose .outs[i] and
+    .sizes[i] receive field i's stream and size on each run()."""
+    n = len(xs)
+    ebs = list(ebs) if hasattr(ebs, "__len__") else [ebs] * n
+    modes = list(modes) if isinstance(modes, (list, tuple)) else [modes] * n
+    dims = dims or [tuple(x.shape) if x.dim() else (1,) for x in xs]
+    arr = (SzCField * n)()
+    outs = outs or []
+    sizes = sizes or []
+    for i, x in enumerate(xs):
+        if not (x.is_cuda and x.is_contiguous() and x.dtype in (torch.float32, torch.float64)):
+            raise ValueError("batch inputs must be contiguous float32/float64 device tensors")
+        p = make_params(x.dtype, dims[i], ebs[i], modes[i], block)
+        cap = int(lib().sz_compress_bound(ctypes.byref(p)))
+        if len(outs) <= i:
+            outs.append(torch.empty(cap, dtype=torch.uint8, device=x.device))
+        if len(sizes) <= i:
+            sizes.append(torch.zeros(1, dtype=torch.uint64, device=x.device))
+        arr[i].params = p
+        arr[i].d_in = x.data_ptr()
+        arr[i].d_out = outs[i].data_ptr()
+        arr[i].out_cap = outs[i].numel()
+        arr[i].d_out_size = sizes[i].data_ptr()
+    wsz = int(lib().sz_batch_workspace_size(arr, None, n))
+    if wsz == 0:
+        raise SzError(1, "invalid batch: " + lib().sz_last_error().decode())
+    if ws is None:
+        ws = torch.empty(wsz, dtype=torch.uint8, device=xs[0].device)
+    h = ctypes.c_void_p()
+    _check(lib().sz_batch_create_compress(arr, n, _ptr(ws), ws.numel(), ctypes.byref(h)), "sz_batch_create_compress")
+    return Batch(h, ws, (list(xs), arr), outs=outs, sizes=sizes)
+
+
+def decompress_batch(streams, nbytes, expected, outs=None, statuses=None, ws=None):
+    """Plan a decompression batch over device streams (uint8 tensors of
+    nbytes[i] valid bytes) with per-field expected params (dicts as returned
+    by inspect()). Returns a Batch with .outs[i] and .statuses[i]."""
+    n = len(streams)
+    arr = (SzDField * n)()
+    outs = outs or []
+    statuses = statuses or []
+    for i, d in enumerate(streams):
+        e = expected[i]
+        p = make_params(e["dtype"], e["dims"], e.get("eb", 0.0), e.get("mode", "rel"), e["block"])
+        cnt = 1
+        for v in e["dims"]:
+            cnt *= int(v)
+        dt = torch.float32 if p.dtype == SZ_F32 else torch.float64
+        if len(outs) <= i:
+            outs.append(torch.empty(max(cnt, 1), dtype=dt, device=d.device))
+        if len(statuses) <= i:
+            statuses.append(torch.zeros(1, dtype=torch.uint32, device=d.device))
+        arr[i].expected = p
+        arr[i].d_in = d.data_ptr()
+        arr[i].in_bytes = int(nbytes[i])
+        arr[i].d_out = outs[i].data_ptr()
+        arr[i].out_cap = outs[i].numel() * outs[i].element_size()
+        arr[i].d_status = statuses[i].data_ptr()
+    wsz = int(lib().sz_batch_workspace_size(None, arr, n))
+    if wsz == 0:
+        raise SzError(1, "invalid batch: " + lib().sz_last_error().decode())
+    if ws is None:
+        ws = torch.empty(wsz, dtype=torch.uint8, device=streams[0].device)
+    h = ctypes.c_void_p()
+    _check(lib().sz_batch_create_decompress(arr, n, _ptr(ws), ws.numel(), ctypes.byref(h)),
+           "sz_batch_create_decompress")
+    return Batch(h, ws, (list(streams), arr), outs=outs, statuses=statuses)
