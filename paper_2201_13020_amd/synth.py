@@ -150,3 +150,142 @@ def make(name, shape=None, field=0):
     if c["gen"] == "qc_state_1d":
         return qc_state_1d(shape[0], field)
     raise KeyError(name)
+
+
+# ------------------------------------------------------- many-field batches --
+#
+# A batch of fields of uneven sizes and both element types (the workload of
+# the batched path). The specs come from numpy default_rng(13020 + 1000 * 6);
+# each field's values come from torch's generator seeded with 13020 + 6000 +
+# index, on whatever device the caller names (the full batch is several GiB,
+# so it is generated where it is used). The content follows the generators
+# above: 1-D fields are sums of sines with noise, 2-D and 3-D fields are
+# Gaussian random fields with a k^(-5/3) energy spectrum, half of them with
+# exact-zero regions.
+
+_BATCH_CFG = 6
+
+
+def batch_specs(count=4096, median=1 << 20, sigma=1.25, lo=4 << 10, hi=64 << 20, f64_frac=0.2,
+                ebs=(1e-2, 1e-3, 1e-4), seed_cfg=_BATCH_CFG):
+    """Field specs: byte size ~ LogNormal(ln median, sigma) redrawn until it
+    lies in [lo, hi]; float64 with probability f64_frac; 1 to 3 dims with
+    log-uniform aspect ratios in [1/8, 8] (the element count is the product of
+    the dims); a relative bound drawn from ebs."""
+    r = _rng(seed_cfg, 0)
+    specs = []
+    for i in range(count):
+        while True:
+            s = float(np.exp(r.normal(np.log(median), sigma)))
+            if lo <= s <= hi:
+                break
+        f64 = r.random() < f64_frac
+        w = 8 if f64 else 4
+        n0 = max(1, int(s) // w)
+        nd = int(r.integers(1, 4))
+        if nd == 1:
+            dims = (n0,)
+        else:
+            a = r.uniform(np.log(1 / 8), np.log(8), nd)
+            a -= a.mean()
+            base = np.log(n0) / nd
+            dims = tuple(max(1, int(round(float(np.exp(base + ai))))) for ai in a)
+        eb = float(ebs[int(r.integers(0, len(ebs)))])
+        zero = nd > 1 and r.random() < 0.5
+        specs.append(dict(index=i, dims=dims, dtype="float64" if f64 else "float32", eb=eb,
+                          zero_regions=bool(zero), seed=13020 + 1000 * seed_cfg + i))
+    return specs
+
+
+def spec_elems(spec):
+    n = 1
+    for d in spec["dims"]:
+        n *= int(d)
+    return n
+
+
+def _torch_spectral(shape, g, slope, device):
+    import torch
+    white = torch.randn(shape, generator=g, device=device, dtype=torch.float64)
+    F = torch.fft.rfftn(white)
+    del white
+    ks = [torch.fft.fftfreq(s, device=device, dtype=torch.float64) for s in shape[:-1]]
+    ks.append(torch.fft.rfftfreq(shape[-1], device=device, dtype=torch.float64))
+    k2 = torch.zeros((), device=device, dtype=torch.float64)
+    for ax, k in enumerate(ks):
+        view = [1] * len(shape)
+        view[ax] = k.numel()
+        k2 = k2 + (k * k).view(view)
+    amp = torch.where(k2 > 0, k2.clamp_min(1e-300) ** (slope / 2.0), torch.zeros_like(k2))
+    x = torch.fft.irfftn(F * amp, s=shape)
+    x -= x.mean()
+    sd = x.std()
+    if sd > 0:
+        x /= sd
+    return x
+
+
+def batch_field(spec, device="cpu"):
+    """Values of one batch field as a contiguous torch tensor of the spec's
+    dims and element type on `device`."""
+    import torch
+    if torch.device(device).type == "cuda":
+        # thousands of distinct shapes: keep few FFT plans (and their workspaces)
+        torch.backends.cuda.cufft_plan_cache[torch.device(device).index or 0].max_size = 8
+    g = torch.Generator(device=device)
+    g.manual_seed(spec["seed"])
+    dims = tuple(int(d) for d in spec["dims"])
+    dt = torch.float64 if spec["dtype"] == "float64" else torch.float32
+    if len(dims) == 1:
+        n = dims[0]
+        u = torch.rand(16, generator=g, device=device, dtype=torch.float64)
+        f = torch.exp(u[:8] * np.log(4096.0))
+        ph = u[8:] * (2 * np.pi)
+        t = torch.arange(n, device=device, dtype=torch.float64) / n
+        x = torch.zeros(n, device=device, dtype=torch.float64)
+        for j in range(8):
+            x += torch.sin(2 * np.pi * f[j] * t + ph[j])
+        x += 1e-3 * torch.randn(n, generator=g, device=device, dtype=torch.float64)
+    else:
+        x = _torch_spectral(dims, g, -11.0 / 6.0, device)
+        if spec["zero_regions"]:
+            m = _torch_spectral(dims, g, -3.0, device)
+            flat = m.reshape(-1)
+            step = max(1, flat.numel() // (1 << 20))
+            thr = torch.quantile(flat[::step], 0.2)
+            x[m < thr] = 0.0
+    return x.to(dt).contiguous()
+
+
+# ----------------------------------------------------------- serving traces --
+#
+# Requests of the serving workload: Poisson arrivals at a given rate, 60 %
+# compressions and 40 % decompressions, byte sizes ~ LogNormal(ln 4 MiB, 1.5)
+# redrawn until in [64 KiB, 256 MiB], float64 with probability 0.2. A
+# compression reads a slice of a pre-generated device field of its element
+# type (offset given as a fraction of the free room); a decompression reads a
+# resident item picked by a uniform draw. numpy default_rng(13020 + 7000 +
+# seed).
+
+_SERVE_CFG = 7
+
+
+def serve_trace(count, rate, seed=0, median=4 << 20, sigma=1.5, lo=64 << 10, hi=256 << 20, f64_frac=0.2,
+                compress_frac=0.6):
+    """Arrays of one trace: t (seconds from the start), kind (0 compress,
+    1 decompress), nbytes, f64 (bool), pos (uniform [0, 1): slice offset or
+    item pick)."""
+    r = _rng(_SERVE_CFG, seed)
+    gaps = r.exponential(1.0 / rate, count) if rate > 0 else np.zeros(count)
+    t = np.cumsum(gaps) - gaps[0]
+    kind = (r.random(count) >= compress_frac).astype(np.int32)
+    nbytes = np.empty(count, dtype=np.int64)
+    for i in range(count):
+        while True:
+            s = float(np.exp(r.normal(np.log(median), sigma)))
+            if lo <= s <= hi:
+                break
+        nbytes[i] = int(s)
+    f64 = r.random(count) < f64_frac
+    pos = r.random(count)
+    return dict(t=t, kind=kind, nbytes=nbytes, f64=f64, pos=pos)
