@@ -54,7 +54,16 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile", action="store_true",
                     help="short eager run for profilers: no CPU baseline, no instrumented pass, plus a plain 256 MiB copy whose HBM counters scale the others")
-    ap.add_argument("--field", type=str, default="cfg2", choices=sorted(FIELDS))
+    ap.add_argument("--field", type=str, default="cfg2", choices=sorted(FIELDS) + ["cfg4", "cfg5"],
+                    help="cfg4: the many-field batch (batched launches vs per-field calls); "
+                         "cfg5: the serving loop (continuous batching vs serial FIFO)")
+    ap.add_argument("--batch-fields", type=int, default=4096, help="cfg4: number of fields")
+    ap.add_argument("--tune", action="store_true", help="cfg4: autotune the encode geometry first")
+    ap.add_argument("--cpu-sample-fields", type=int, default=48, help="cfg4: fields the oracle runs on")
+    ap.add_argument("--serve-requests", type=int, default=2000, help="cfg5: requests per load level")
+    ap.add_argument("--serve-slots", type=int, default=4, help="cfg5: streams of the batching server")
+    ap.add_argument("--serve-max-batch", type=int, default=64, help="cfg5: requests per launch group")
+    ap.add_argument("--serve-budget-gib", type=int, default=64, help="cfg5: HBM budget of the server")
     return ap.parse_args()
 
 
@@ -112,13 +121,17 @@ def recorded_traffic(kernel, tag="cfg2"):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is design-only)"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1 (sharding over several GPUs is a design, not built)"}))
         sys.exit(2)
     import numpy as np
     import torch
     from paper_2201_13020_amd import synth, szx
 
     assert torch.cuda.is_available(), "bench needs a GPU"
+    if args.field == "cfg4":
+        return bench_batch(args)
+    if args.field == "cfg5":
+        return bench_serve(args)
     dev = torch.device("cuda:0")
     global BOUNDS
     field = FIELDS[args.field]
@@ -321,6 +334,315 @@ def main():
         for _ in range(3):
             b.copy_(a)
         torch.cuda.synchronize()
+    print(json.dumps(result), flush=True)
+
+
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def bench_batch(args):
+    """Many fields of uneven sizes and both element types: one graph-replayed
+    batch launch per direction against per-field calls (eager, and captured
+    into one graph), every field's stream checked equal between the two and a
+    sample against the oracle."""
+    import ctypes
+    import struct
+
+    import numpy as np
+    import torch
+    from paper_2201_13020_amd import synth, szx, tune
+
+    dev = torch.device("cuda:0")
+    specs = synth.batch_specs(args.batch_fields)
+    t0 = time.perf_counter()
+    xs = [synth.batch_field(sp, dev) for sp in specs]
+    torch.cuda.synchronize()
+    _log(f"generated {len(xs)} fields in {time.perf_counter() - t0:.1f} s")
+    nbytes = [x.numel() * x.element_size() for x in xs]
+    total = sum(nbytes)
+    by_dtype = {"float32": 0, "float64": 0}
+    for sp, nb in zip(specs, nbytes):
+        by_dtype[sp["dtype"]] += nb
+    ebs = [sp["eb"] for sp in specs]
+    dims = [sp["dims"] for sp in specs]
+    tuned_from_cache = tune.apply_cache()
+
+    cb = szx.compress_batch(xs, ebs, "rel", BLOCK, dims=dims)
+    tuning = None
+    if args.tune:
+        res = tune.tune_batch(cb, by_dtype, BLOCK)
+        tuning = {dt: {"encode_wgs": r[0], "ms": round(r[1], 4),
+                       "candidates_ms": {str(k): round(v, 4) for k, v in r[2].items()}} for dt, r in res.items()}
+        _log(f"tuned {tuning}")
+    cb.run()
+    torch.cuda.synchronize()
+    lens = torch.stack(cb.sizes).cpu().view(torch.int64).reshape(-1).tolist()
+    assert all(l > 0 for l in lens), "a batch field failed to compress"
+    comp_total = sum(lens)
+    heads = torch.stack([o[:96] for o in cb.outs]).cpu().numpy()
+    exps = [szx.inspect(h.tobytes()) for h in heads]
+    db = szx.decompress_batch(cb.outs, lens, exps)
+    db.run()
+    torch.cuda.synchronize()
+    assert all(int(v) == 0 for v in torch.stack(db.statuses).cpu().view(torch.int32).reshape(-1)), "decode status"
+
+    # per-field calls into their own buffers, parameter structs built before timing
+    ws = torch.empty(max(szx.workspace_size(x.dtype, d, 1e-3, "rel", BLOCK) for x, d in zip(xs, dims)),
+                     dtype=torch.uint8, device=dev)
+    pf_out = [torch.empty_like(o) for o in cb.outs]
+    pf_size = [torch.zeros(1, dtype=torch.uint64, device=dev) for _ in xs]
+    pf_y = [torch.empty_like(y) for y in db.outs]
+    pf_st = torch.zeros(1, dtype=torch.uint32, device=dev)
+    cparams = [szx.make_params(x.dtype, d, eb, "rel", BLOCK) for x, d, eb in zip(xs, dims, ebs)]
+    L = szx.lib()
+
+    def per_field_compress():
+        sh = szx._stream_handle(None)
+        for i, x in enumerate(xs):
+            rc = L.sz_compress(ctypes.byref(cparams[i]), x.data_ptr(), pf_out[i].data_ptr(), pf_out[i].numel(),
+                               pf_size[i].data_ptr(), ws.data_ptr(), ws.numel(), sh)
+            assert rc == 0, L.sz_last_error()
+
+    def per_field_decompress():
+        sh = szx._stream_handle(None)
+        for i in range(len(xs)):
+            rc = L.sz_decompress(cb.outs[i].data_ptr(), lens[i], ctypes.byref(cparams[i]), pf_y[i].data_ptr(),
+                                 pf_y[i].numel() * pf_y[i].element_size(), pf_st.data_ptr(), ws.data_ptr(),
+                                 ws.numel(), sh)
+            assert rc == 0, L.sz_last_error()
+
+    per_field_compress()
+    per_field_decompress()
+    torch.cuda.synchronize()
+    same = all(torch.equal(cb.outs[i][:lens[i]], pf_out[i][:lens[i]]) for i in range(len(xs)))
+    same = same and torch.stack(pf_size).cpu().view(torch.int64).reshape(-1).tolist() == lens
+    same_y = all(torch.equal(db.outs[i].view(torch.uint8), pf_y[i].view(torch.uint8)) for i in range(len(xs)))
+    assert same and same_y, "batch and per-field outputs differ"
+    _log("batch output == per-field output for every field")
+
+    def capture(fn):
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            fn()
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            fn()
+        torch.cuda.synchronize()
+        return g
+
+    g_c = capture(cb.run)
+    g_d = capture(db.run)
+    t0 = time.perf_counter()
+    g_pfc = capture(per_field_compress)
+    g_pfd = capture(per_field_decompress)
+    _log(f"captured per-field graphs in {time.perf_counter() - t0:.1f} s")
+
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            fn()
+        b.record()
+        b.synchronize()
+        return a.elapsed_time(b) / steps
+
+    steps, warm = args.steps, args.warmup
+    for _ in range(warm):
+        g_c.replay()
+        g_d.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g_c.replay()
+        g_d.replay()
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) * 1e3 / steps
+    _log(f"timed {steps} batched steps: {ms_step:.3f} ms each")
+    ms = {
+        "batch_compress": timed(g_c.replay, steps, 2),
+        "batch_decompress": timed(g_d.replay, steps, 2),
+        "per_field_graph_compress": timed(g_pfc.replay, max(3, steps // 4), 1),
+        "per_field_graph_decompress": timed(g_pfd.replay, max(3, steps // 4), 1),
+        "per_field_eager_compress": timed(per_field_compress, 3, 1),
+        "per_field_eager_decompress": timed(per_field_decompress, 3, 1),
+    }
+    gbps = {k: round(total / v / 1e6, 1) for k, v in ms.items()}
+    _log(f"GB/s {gbps}")
+
+    # kernel durations of the batched launches (HIP events around each launch)
+    szx.timing_enable(True)
+    szx.timing_read()
+    for _ in range(steps):
+        cb.run()
+        db.run()
+    torch.cuda.synchronize()
+    kt = szx.timing_read()
+    szx.timing_enable(False)
+    alg = {}
+    for i, x in enumerate(xs):
+        nblk, n_nc, mid_total = struct.unpack_from("<3Q", heads[i].tobytes(), 72)
+        for k in ("k_stats", "k_classify", "k_encode", "k_dindex", "k_decode"):
+            alg[k] = alg.get(k, 0) + kernel_bytes(k, x.numel(), x.element_size(), nblk, n_nc, mid_total)
+    kernels = {}
+    for name, (cnt, kms) in kt.items():
+        per_run_ms = kms / steps
+        a = alg.get(name, 0)
+        kernels[name] = {"launches_per_run": cnt // steps, "us_per_run": round(per_run_ms * 1e3, 1),
+                         "alg_bytes_per_run": int(a), "achieved_GBps": round(a / per_run_ms / 1e6, 1) if a else None}
+    dom = max((k for k in kernels if kernels[k]["alg_bytes_per_run"]), key=lambda k: kernels[k]["us_per_run"])
+    kd = kernels[dom]
+
+    cpu = None
+    if not args.no_cpu_baseline and args.cpu_sample_fields > 0:
+        from oracle import szref
+        r = np.random.default_rng(5)
+        pick = sorted(r.choice(len(xs), size=min(args.cpu_sample_fields, len(xs)), replace=False).tolist())
+        tc = td = 0.0
+        sb = 0
+        for i in pick:
+            xh = xs[i].cpu().numpy()
+            t1 = time.perf_counter()
+            ref = szref.compress(xh, ebs[i], "rel", BLOCK)
+            t2 = time.perf_counter()
+            yref = szref.decompress(ref)
+            t3 = time.perf_counter()
+            tc += t2 - t1
+            td += t3 - t2
+            sb += xh.nbytes
+            assert np.array_equal(cb.outs[i][:lens[i]].cpu().numpy(), ref), f"field {i} differs from the oracle"
+            udt = np.uint32 if xh.itemsize == 4 else np.uint64
+            yb = db.outs[i].cpu().numpy()
+            assert np.array_equal(yb.view(udt), yref.ravel().view(udt)), f"field {i} decode differs from the oracle"
+        cpu = {"value": round(2 * sb / (tc + td) / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+               "sample": f"{len(pick)} fields of the batch drawn at random ({sb / 2**20:.0f} MiB), compress + "
+                         f"decompress each, single thread; matched the batch output byte for byte",
+               "seconds": round(tc + td, 3)}
+        _log(f"oracle sample of {len(pick)} fields matched")
+
+    result = {
+        "metric": "compress & decompress GB/s (uncompressed) and % of HBM peak; ratio",
+        "value": round(2 * total / ms_step / 1e6, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warm,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"{len(xs)} fields, sizes lognormal 4 KiB-64 MiB (median 1 MiB), "
+                               f"{100 * by_dtype['float64'] / total:.0f}% of bytes float64, 1-3 dims, REL "
+                               "1e-2/1e-3/1e-4 per field, block 128; one step = batched compress + batched decompress",
+                   "fields": len(xs), "bytes": total, "block": BLOCK, "parallelism": "single GPU",
+                   "launch": "hip graph replay, one launch per pass and element type"},
+        "detail": {
+            "ratio": round(total / comp_total, 4),
+            "ms": {k: round(v, 4) for k, v in ms.items()},
+            "GBps_uncompressed": gbps,
+            "hbm_frac_uncompressed": {k: round(v / HBM_PEAK_GBPS, 4) for k, v in gbps.items()},
+            "batch_speedup_vs_per_field_graph": {
+                "compress": round(ms["per_field_graph_compress"] / ms["batch_compress"], 2),
+                "decompress": round(ms["per_field_graph_decompress"] / ms["batch_decompress"], 2)},
+            "batch_speedup_vs_per_field_eager": {
+                "compress": round(ms["per_field_eager_compress"] / ms["batch_compress"], 2),
+                "decompress": round(ms["per_field_eager_decompress"] / ms["batch_decompress"], 2)},
+            "kernels": kernels,
+            "tuning": tuning,
+            "tuned_entries_from_cache": tuned_from_cache,
+        },
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": kd["achieved_GBps"], "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(kd["achieved_GBps"] / HBM_PEAK_GBPS, 4),
+                     "traffic": recorded_traffic(dom, "cfg4"), "alg_bytes_per_run": kd["alg_bytes_per_run"],
+                     "us_per_run": kd["us_per_run"], "launches_per_run": kd["launches_per_run"]},
+    }
+    if cpu is not None:
+        result["cpu_baseline"] = cpu
+    print(json.dumps(result), flush=True)
+
+
+def bench_serve(args):
+    """Serving: Poisson-arriving compress/decompress requests against the
+    continuous-batching server and against a serial FIFO server (one slot,
+    one request per launch), at rates relative to the serial capacity."""
+    import numpy as np
+    import torch
+    from paper_2201_13020_amd import serve, synth
+
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    bases = {False: synth.batch_field(dict(dims=(256, 512, 512), dtype="float32", eb=1e-3, zero_regions=True,
+                                           seed=13020 + 7100), dev).reshape(-1),
+             True: synth.batch_field(dict(dims=(128, 512, 512), dtype="float64", eb=1e-3, zero_regions=True,
+                                          seed=13020 + 7101), dev).reshape(-1)}
+    torch.cuda.synchronize()
+    _log(f"generated base fields in {time.perf_counter() - t0:.1f} s")
+    n_req = args.serve_requests
+    warm = synth.serve_trace(256, 0.0, seed=1)
+    warm["kind"][:] = 0
+    policies = {"continuous_batching": dict(slots=args.serve_slots, max_batch=args.serve_max_batch),
+                "serial_fifo": dict(slots=1, max_batch=1)}
+    levels = [0.25, 0.5, 0.75, 0.9, 1.0, 1.1, 1.25]
+    out = {}
+    capacity = {}
+    for name in ("serial_fifo", "continuous_batching"):
+        pol = policies[name]
+        with serve.Server(hbm_budget=args.serve_budget_gib << 30, block=BLOCK, **pol) as srv:
+            _, pool = serve.replay(srv, warm, bases)
+            sat = synth.serve_trace(n_req, 0.0, seed=2)
+            done, pool = serve.replay(srv, sat, bases, warm_items=pool)
+            s = serve.summarize(done)
+            span = (max(c["t_done"] for c in done) - min(c["t_arrival"] for c in done)) / 1e9
+            capacity[name] = dict(req_per_s=round(len(done) / span, 1), **s)
+            _log(f"{name} saturated: {capacity[name]}")
+            if name == "serial_fifo":
+                base_rate = len(done) / span
+            rows = {}
+            for lv in levels:
+                tr = synth.serve_trace(n_req, lv * base_rate, seed=100 + int(lv * 100))
+                done, pool = serve.replay(srv, tr, bases, warm_items=pool)
+                rows[str(lv)] = serve.summarize(done)
+                _log(f"{name} load {lv}: {rows[str(lv)]}")
+            st = srv.stats()
+            out[name] = dict(levels=rows, arena_peak_GiB=round(st["arena_peak"] / 2**30, 2),
+                             groups_launched=st["groups_launched"])
+    cb, sf = out["continuous_batching"]["levels"], out["serial_fifo"]["levels"]
+    result = {
+        "metric": "compress & decompress GB/s (uncompressed) and % of HBM peak; ratio",
+        "value": capacity["continuous_batching"]["GBps"],
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": n_req,
+        "warmup": 256,
+        "ms_per_step": round(1e3 / capacity["continuous_batching"]["req_per_s"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "serving: Poisson arrivals, 60% compress / 40% decompress of resident streams, "
+                               "sizes lognormal 64 KiB-256 MiB (median 4 MiB), 20% float64, REL 1e-3, block 128, "
+                               f"HBM budget {args.serve_budget_gib} GiB; value = saturated continuous-batching "
+                               "throughput (all requests queued at once)",
+                   "requests_per_level": n_req, "slots": args.serve_slots, "max_batch": args.serve_max_batch,
+                   "parallelism": "single GPU"},
+        "detail": {
+            "capacity": capacity,
+            "load_levels_x_serial_capacity": levels,
+            "serial_capacity_req_per_s": capacity["serial_fifo"]["req_per_s"],
+            "policies": out,
+            "p99_ms_ratio_serial_over_batching": {lv: round(sf[lv]["p99_ms"] / cb[lv]["p99_ms"], 2) for lv in cb},
+        },
+    }
     print(json.dumps(result), flush=True)
 
 

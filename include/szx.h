@@ -153,9 +153,23 @@ sz_status sz_batch_create_compress(const sz_cfield* fields, uint32_t n, void* d_
 sz_status sz_batch_create_decompress(const sz_dfield* fields, uint32_t n, void* d_ws, uint64_t ws_bytes,
                                      sz_batch* out);
 
-/* Launch geometry of a compression batch: persistent workgroups of the encode
-   pass (the autotuner's knob; no effect on the output bytes). */
-sz_status sz_batch_set_geometry(sz_batch b, uint32_t encode_wgs);
+/* Launch geometry of the encode pass of a compression batch for the fields of
+   one element type: the number of persistent workgroups (the autotuner's
+   knob; no effect on the output bytes; values below 8 act as 8, one per
+   ticket class of the encoder). A new batch starts from the
+   process-wide table of sz_set_geometry for the size class of that type's
+   total input bytes. */
+sz_status sz_batch_set_geometry(sz_batch b, sz_dtype dtype, uint32_t encode_wgs);
+
+/* Size class of an input of `bytes` bytes for launch-geometry tables:
+   0 below 256 KiB, then one class per factor 4, 7 from 1 GiB up. */
+uint32_t sz_size_class(uint64_t bytes);
+
+/* Process-wide encode geometry for inputs of one element type and size class,
+   used by sz_compress and as the starting geometry of new batches;
+   encode_wgs = 0 restores the default (4 per compute unit). Thread-safe;
+   no effect on the output bytes. */
+sz_status sz_set_geometry(sz_dtype dtype, uint32_t size_class, uint32_t encode_wgs);
 
 /* Enqueue every pass of the batch on `stream`. */
 sz_status sz_batch_run(sz_batch b, hipStream_t stream);

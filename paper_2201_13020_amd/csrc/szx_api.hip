@@ -5,15 +5,17 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <mutex>
 #include <string>
 #include <vector>
 
 #include "../../include/szx.h"
-#include "szx_launch.hpp"
+#include "szx_host.hpp"
 
-namespace {
+namespace szx {
+namespace host {
 
 thread_local std::string g_err;
 
@@ -21,6 +23,8 @@ sz_status fail(sz_status s, const std::string& msg) {
   g_err = msg;
   return s;
 }
+
+void clear_error() { g_err.clear(); }
 
 bool is_pow2_block(uint32_t b) { return b >= 8 && b <= 1024 && (b & (b - 1)) == 0; }
 
@@ -81,23 +85,27 @@ struct TimedLaunch {
 std::mutex g_tmu;
 bool g_timing = false;
 std::vector<TimedLaunch> g_open;  // recorded, not yet read
-hipEvent_t g_pending_begin = nullptr;
+std::vector<std::pair<hipStream_t, hipEvent_t>> g_pending;  // begin events by stream
 
 void timer_hook(const char* name, hipStream_t s, int begin) {
   std::lock_guard<std::mutex> lock(g_tmu);
+  hipEvent_t e;
+  hipEventCreate(&e);
+  hipEventRecord(e, s);
   if (begin) {
-    hipEventCreate(&g_pending_begin);
-    hipEventRecord(g_pending_begin, s);
-  } else {
-    hipEvent_t e;
-    hipEventCreate(&e);
-    hipEventRecord(e, s);
-    g_open.push_back({name, g_pending_begin, e});
-    g_pending_begin = nullptr;
+    g_pending.push_back({s, e});
+    return;
   }
+  for (size_t i = g_pending.size(); i-- > 0;) {
+    if (g_pending[i].first != s) continue;
+    g_open.push_back({name, g_pending[i].second, e});
+    g_pending.erase(g_pending.begin() + i);
+    return;
+  }
+  hipEventDestroy(e);
 }
 
-szx::TimerHook current_hook() {
+TimerHook current_hook() {
   std::lock_guard<std::mutex> lock(g_tmu);
   return g_timing ? timer_hook : nullptr;
 }
@@ -124,12 +132,12 @@ szx::FieldC single_field_c(const szx::Job& j, const void* in, void* out, uint64_
   f.ndims = j.ndims;
   f.b = j.b;
   f.ctr = (szx::Counters*)(ws + W.counters);
+  f.range = (uint64_t*)(ws + W.range);
+  f.nslots = szx::range_slots(ft.chunks);
   f.stats = ws + W.stats;
-  f.part = (uint64_t*)(ws + W.part);
   f.enc_r0 = (uint64_t*)(ws + W.enc_r0);
   f.cls_status = (uint64_t*)(ws + W.cls_status);
   f.enc_mid = (uint64_t*)(ws + W.enc_mid);
-  f.nparts = (uint32_t)ft.chunks;
   return f;
 }
 
@@ -153,13 +161,34 @@ szx::FieldD single_field_d(const szx::Job& j, const void* in, uint64_t in_bytes,
   return f;
 }
 
-szx::CLaunchGeom default_geom(int ncu) {
-  szx::CLaunchGeom g;
-  g.encode_wgs = (uint32_t)ncu * 4;
+// Process-wide encode geometry per element type and size class (0: default).
+constexpr uint32_t kSizeClasses = 8;
+std::atomic<uint32_t> g_geom[2][kSizeClasses];
+
+uint32_t size_class_of(uint64_t bytes) {
+  uint32_t c = 0;
+  for (uint64_t lim = 256ull << 10; c + 1 < kSizeClasses && bytes >= lim; lim <<= 2) ++c;
+  return c;
+}
+
+uint32_t encode_wgs_for(uint32_t dtype, uint64_t bytes, int ncu) {
+  const uint32_t v = g_geom[dtype][size_class_of(bytes)].load(std::memory_order_relaxed);
+  return v ? v : (uint32_t)ncu * 4;
+}
+
+CLaunchGeom batch_geom(const sz_cfield* fs, uint32_t n, int ncu) {
+  uint64_t bytes[2] = {0, 0};
+  for (uint32_t i = 0; i < n; ++i) {
+    Job j;
+    if (make_job(&fs[i].params, j) == SZ_OK) bytes[j.dtype] += j.n * j.w;
+  }
+  CLaunchGeom g;
+  for (int dt = 0; dt < 2; ++dt) g.encode_wgs[dt] = encode_wgs_for(dt, bytes[dt], ncu);
   return g;
 }
 
-}  // namespace
+}  // namespace host
+}  // namespace szx
 
 // Host handle of a planned batch (descriptors already in the workspace).
 struct sz_batch_s {
@@ -170,18 +199,12 @@ struct sz_batch_s {
   szx::CLaunchGeom geom;
 };
 
+namespace szx {
+namespace host {
+
 namespace {
-
-uint64_t a256(uint64_t x) { return szx::align256(x); }
-
-// Byte layout of a batch workspace; fills descriptors when `host` is given.
-// Map m = 2 * pass + element type; compress passes: extrema chunks,
-// classification, encode; decompress passes: index, decode.
-struct BatchPlan {
-  uint64_t fields_off, maps_off[6], zero_off, zero_end, total;
-  uint64_t tiles[6];
-  int nmaps;
-};
+uint64_t a256(uint64_t x) { return align256(x); }
+}  // namespace
 
 sz_status check_batch_common(uint32_t n, uint32_t block, const sz_params* p) {
   if (n == 0) return fail(SZ_EINVAL, "empty batch");
@@ -190,7 +213,7 @@ sz_status check_batch_common(uint32_t n, uint32_t block, const sz_params* p) {
 }
 
 sz_status plan_compress(const sz_cfield* fs, uint32_t n, uint8_t* ws, std::vector<uint8_t>* host, BatchPlan& P,
-                        sz_batch_s* hb) {
+                        CBatch* bout, uint32_t* block_out) {
   if (!fs || n == 0) return fail(SZ_EINVAL, "empty batch");
   std::vector<szx::Job> jobs(n);
   const uint32_t block = fs[0].params.block_size;
@@ -220,18 +243,16 @@ sz_status plan_compress(const sz_cfield* fs, uint32_t n, uint8_t* ws, std::vecto
   for (uint32_t i = 0; i < n; ++i) {
     const szx::FieldTiles ft = szx::field_tiles(jobs[i].n, jobs[i].nblk, jobs[i].w, block);
     ctr_off[i] = off;
-    off = a256(off + 256);
+    off = a256(off + 256 + (uint64_t)szx::range_slots(ft.chunks) * szx::kRangeStride);
     cls_off[i] = off;
     off = a256(off + (ft.cls + 1) * 8);
     mid_off[i] = off;
     off = a256(off + (ft.enc + 1) * 8);
   }
   P.zero_end = off;
-  std::vector<uint64_t> part_off(n), stats_off(n), r0_off(n);
+  std::vector<uint64_t> stats_off(n), r0_off(n);
   for (uint32_t i = 0; i < n; ++i) {
     const szx::FieldTiles ft = szx::field_tiles(jobs[i].n, jobs[i].nblk, jobs[i].w, block);
-    part_off[i] = off;
-    off = a256(off + (ft.chunks + 1) * 16);
     stats_off[i] = off;
     off = a256(off + jobs[i].nblk * 2 * (uint64_t)jobs[i].w);
     r0_off[i] = off;
@@ -267,12 +288,12 @@ sz_status plan_compress(const sz_cfield* fs, uint32_t n, uint8_t* ws, std::vecto
     f.ndims = j.ndims;
     f.b = j.b;
     f.ctr = (szx::Counters*)(ws + ctr_off[i]);
+    f.range = (uint64_t*)(ws + ctr_off[i] + 256);
+    f.nslots = szx::range_slots(ft.chunks);
     f.stats = ws + stats_off[i];
-    f.part = (uint64_t*)(ws + part_off[i]);
     f.enc_r0 = (uint64_t*)(ws + r0_off[i]);
     f.cls_status = (uint64_t*)(ws + cls_off[i]);
     f.enc_mid = (uint64_t*)(ws + mid_off[i]);
-    f.nparts = (uint32_t)ft.chunks;
     const uint32_t dt = j.dtype;
     f.base_stats = bc[dt];
     f.base_cls = bl[dt];
@@ -285,7 +306,7 @@ sz_status plan_compress(const sz_cfield* fs, uint32_t n, uint8_t* ws, std::vecto
     bl[dt] += ft.cls;
     be[dt] += ft.enc;
   }
-  szx::CBatch& b = hb->cb;
+  szx::CBatch& b = *bout;
   memset(&b, 0, sizeof b);
   b.fields = (const szx::FieldC*)(ws + P.fields_off);
   for (int dt = 0; dt < 2; ++dt) {
@@ -300,12 +321,12 @@ sz_status plan_compress(const sz_cfield* fs, uint32_t n, uint8_t* ws, std::vecto
   b.zero_begin = (uint64_t*)(ws + P.zero_off);
   b.zero_words = (P.zero_end - P.zero_off) / 8;
   b.nfields = n;
-  hb->block = block;
+  *block_out = block;
   return SZ_OK;
 }
 
 sz_status plan_decompress(const sz_dfield* fs, uint32_t n, uint8_t* ws, std::vector<uint8_t>* host, BatchPlan& P,
-                          sz_batch_s* hb) {
+                          DBatch* bout, uint32_t* block_out) {
   if (!fs || n == 0) return fail(SZ_EINVAL, "empty batch");
   std::vector<szx::Job> jobs(n);
   const uint32_t block = fs[0].expected.block_size;
@@ -379,7 +400,7 @@ sz_status plan_decompress(const sz_dfield* fs, uint32_t n, uint8_t* ws, std::vec
     bi[dt] += ft.cls;
     bd[dt] += ft.enc;
   }
-  szx::DBatch& b = hb->db;
+  szx::DBatch& b = *bout;
   memset(&b, 0, sizeof b);
   b.fields = (const szx::FieldD*)(ws + P.fields_off);
   for (int dt = 0; dt < 2; ++dt) {
@@ -391,11 +412,14 @@ sz_status plan_decompress(const sz_dfield* fs, uint32_t n, uint8_t* ws, std::vec
   b.zero_begin = (uint64_t*)(ws + P.zero_off);
   b.zero_words = (P.zero_end - P.zero_off) / 8;
   b.nfields = n;
-  hb->block = block;
+  *block_out = block;
   return SZ_OK;
 }
 
-}  // namespace
+}  // namespace host
+}  // namespace szx
+
+using namespace szx::host;
 
 extern "C" {
 
@@ -437,7 +461,9 @@ sz_status sz_compress(const sz_params* p, const void* d_in, void* d_out, uint64_
   b.zero_begin = (uint64_t*)(ws + W.counters);
   b.zero_words = (W.zero_end - W.counters) / 8;
   b.nfields = 1;
-  const hipError_t e = szx::launch_compress(b, j.b, default_geom(ncu), stream, current_hook());
+  szx::CLaunchGeom g;
+  g.encode_wgs[0] = g.encode_wgs[1] = encode_wgs_for(j.dtype, j.n * j.w, ncu);
+  const hipError_t e = szx::launch_compress(b, j.b, g, stream, current_hook());
   if (e != hipSuccess) return fail(SZ_EDEVICE, std::string("launch failed: ") + hipGetErrorString(e));
   return SZ_OK;
 }
@@ -474,9 +500,9 @@ sz_status sz_decompress(const void* d_in, uint64_t in_bytes, const sz_params* ex
 
 uint64_t sz_batch_workspace_size(const sz_cfield* cf, const sz_dfield* df, uint32_t n) {
   BatchPlan P;
-  sz_batch_s tmp;
   if ((cf != nullptr) == (df != nullptr)) return 0;
-  const sz_status s = cf ? plan_compress(cf, n, nullptr, nullptr, P, &tmp) : plan_decompress(df, n, nullptr, nullptr, P, &tmp);
+  const sz_status s = cf ? plan_compress(cf, n, nullptr, nullptr, P, nullptr, nullptr)
+                         : plan_decompress(df, n, nullptr, nullptr, P, nullptr, nullptr);
   return s == SZ_OK ? P.total : 0;
 }
 
@@ -490,10 +516,10 @@ static sz_status batch_create(const sz_cfield* cf, const sz_dfield* df, uint32_t
   sz_batch_s* hb = new sz_batch_s;
   memset(hb, 0, sizeof *hb);
   hb->decompress = df != nullptr;
-  hb->geom = default_geom(ncu);
   BatchPlan P;
   std::vector<uint8_t> host;
-  sz_status s = cf ? plan_compress(cf, n, (uint8_t*)d_ws, &host, P, hb) : plan_decompress(df, n, (uint8_t*)d_ws, &host, P, hb);
+  sz_status s = cf ? plan_compress(cf, n, (uint8_t*)d_ws, &host, P, &hb->cb, &hb->block)
+                   : plan_decompress(df, n, (uint8_t*)d_ws, &host, P, &hb->db, &hb->block);
   if (s == SZ_OK && ws_bytes < P.total) s = fail(SZ_ENOSPC, "workspace below sz_batch_workspace_size");
   if (s == SZ_OK) {
     // descriptors and tile maps, once; run() launches kernels only
@@ -504,6 +530,7 @@ static sz_status batch_create(const sz_cfield* cf, const sz_dfield* df, uint32_t
     delete hb;
     return s;
   }
+  if (cf) hb->geom = batch_geom(cf, n, ncu);
   *out = hb;
   return SZ_OK;
 }
@@ -517,10 +544,21 @@ sz_status sz_batch_create_decompress(const sz_dfield* fields, uint32_t n, void* 
   return batch_create(nullptr, fields, n, d_ws, ws_bytes, out);
 }
 
-sz_status sz_batch_set_geometry(sz_batch b, uint32_t encode_wgs) {
+sz_status sz_batch_set_geometry(sz_batch b, sz_dtype dtype, uint32_t encode_wgs) {
   g_err.clear();
-  if (!b || encode_wgs == 0) return fail(SZ_EINVAL, "bad batch or geometry");
-  b->geom.encode_wgs = encode_wgs;
+  if (!b || b->decompress || encode_wgs == 0 || (dtype != SZ_F32 && dtype != SZ_F64))
+    return fail(SZ_EINVAL, "bad batch or geometry");
+  b->geom.encode_wgs[dtype] = encode_wgs;
+  return SZ_OK;
+}
+
+uint32_t sz_size_class(uint64_t bytes) { return size_class_of(bytes); }
+
+sz_status sz_set_geometry(sz_dtype dtype, uint32_t size_class, uint32_t encode_wgs) {
+  g_err.clear();
+  if ((dtype != SZ_F32 && dtype != SZ_F64) || size_class >= kSizeClasses)
+    return fail(SZ_EINVAL, "bad element type or size class");
+  g_geom[dtype][size_class].store(encode_wgs, std::memory_order_relaxed);
   return SZ_OK;
 }
 

@@ -4,11 +4,12 @@
 // caller's stream; every pass is one launch over all fields of the batch, a
 // single call being a batch of one, so both run the same code):
 //   k_init      clear counters, tickets and the tile status words of the scans
-//   k_stats     per-block totalOrder min/max (Alg. 1 needs both for mu_k) and
-//               per chunk of tiles the finite value range
-//   k_range     the absolute bound e (for the relative bound: eb times the
-//               global finite range, Sec. III footnote), one workgroup a field
-//   k_classify  mid-range mu and constant test of every block (Alg. 1), the
+//   k_stats     per-block totalOrder min/max (Alg. 1 needs both for mu_k); each
+//               workgroup folds its finite value range into the field's
+//               counters (two 64-bit atomic maxima)
+//   k_classify  the absolute bound e (for the relative bound: eb times the
+//               field's finite range, Sec. III footnote), then
+//               mid-range mu and constant test of every block (Alg. 1), the
 //               state bits and the mu section; a light single-pass prefix count
 //               of non-constant blocks gives each encode tile its first rank
 //   k_encode    per non-constant block: normalise, keep K bits (eq. (4)), shift
@@ -27,11 +28,29 @@
 
 namespace szx {
 
-// Field of a call, or of a batch entry, as the kernels see it.
-__device__ __forceinline__ const FieldC& field_at(const CBatch& b, uint32_t f) {
-  return b.fields ? b.fields[f] : b.one;
+// Field of a call, or of a batch entry, as the kernels see it (a copy with
+// its pointers typed as global memory).
+// BATCH: false for a single call (the descriptor is the kernel argument
+// itself), true for a table in memory, else decided at run time.
+enum : int { kAnyCall = -1, kSingle = 0, kBatch = 1 };
+template <int BATCH = kAnyCall>
+__device__ __forceinline__ FieldC field_at(const CBatch& b, uint32_t fi) {
+  FieldC f = BATCH == kSingle ? b.one : BATCH == kBatch ? b.fields[fi] : (b.fields ? b.fields[fi] : b.one);
+  f.in = as_global(f.in);
+  f.out = as_global(f.out);
+  f.out_size = as_global(f.out_size);
+  f.ctr = as_global(f.ctr);
+  f.range = as_global(f.range);
+  f.stats = as_global(f.stats);
+  f.enc_r0 = as_global(f.enc_r0);
+  f.cls_status = as_global(f.cls_status);
+  f.enc_mid = as_global(f.enc_mid);
+  return f;
 }
-__device__ __forceinline__ uint32_t field_of(const uint32_t* map, uint64_t t) { return map ? map[t] : 0u; }
+template <int BATCH = kAnyCall>
+__device__ __forceinline__ uint32_t field_of(const uint32_t* map, uint64_t t) {
+  return BATCH == kSingle ? 0u : BATCH == kBatch ? map[t] : (map ? map[t] : 0u);
+}
 
 // ------------------------------------------------------------------ init ---
 
@@ -94,10 +113,10 @@ __device__ __forceinline__ U group_max(U v) {
 
 // ----------------------------------------------------------------- stats ---
 
-// Per-block totalOrder extrema (as keys) of all values, and per chunk of
-// kStatsChunk tiles the finite range (keys; lo > hi when the chunk saw no
-// finite value) into part[2 * chunk], part[2 * chunk + 1]. A chunk holds tiles
-// of one field; two tiles per iteration keep more loads in flight.
+// Per-block totalOrder extrema (as keys) of all values over a chunk of
+// kStatsChunk tiles of one field (two tiles per iteration keep more loads in
+// flight), and the chunk's finite range folded into one of the field's range
+// slots.
 template <typename T, int B>
 __device__ __forceinline__ void stats_tile(const T (&v)[Geo<T, B>::EPL], int cnt, uint64_t i0, uint64_t nblk,
                                            typename Traits<T>::U* __restrict__ stats,
@@ -160,9 +179,11 @@ __device__ __forceinline__ void stats_chunk(const FieldC& f, uint64_t c, uint64_
       lo = s_lo[i] < lo ? s_lo[i] : lo;
       hi = s_hi[i] > hi ? s_hi[i] : hi;
     }
-    // widen to 64 bits keeping "no finite value" as lo > hi
-    f.part[2 * c] = lo > hi ? ~0ull : lo;
-    f.part[2 * c + 1] = lo > hi ? 0ull : hi;
+    if (lo <= hi) {  // the chunk saw a finite value
+      uint64_t* slot = f.range + (c % f.nslots) * (kRangeStride / 8);
+      atomicMax((unsigned long long*)slot, ~(unsigned long long)lo);
+      atomicMax((unsigned long long*)slot + 1, (unsigned long long)hi);
+    }
   }
 }
 
@@ -170,43 +191,29 @@ template <typename T, int B>
 __global__ __launch_bounds__(256) void k_stats(CBatch b) {
   __shared__ uint64_t s_lo[kWavesPerWG], s_hi[kWavesPerWG];
   const uint64_t g = blockIdx.x;
-  const FieldC& f = field_at(b, field_of(b.field_stats[Traits<T>::BYTES / 8], g));
+  const FieldC f = field_at(b, field_of(b.field_stats[Traits<T>::BYTES / 8], g));
   stats_chunk<T, B>(f, g - f.base_stats, s_lo, s_hi);
 }
 
 // ----------------------------------------------------------------- range ---
 
-// The bound e of each field from its parameters and, for the relative bound,
-// its chunks' finite ranges. One workgroup a field.
-__global__ __launch_bounds__(256) void k_range(CBatch b) {
-  __shared__ uint64_t s_lo[kWavesPerWG], s_hi[kWavesPerWG];
-  const FieldC& f = field_at(b, blockIdx.x);
+// The bound e of a field (as the bits of a T) from its parameters and, for
+// the relative bound, the field's finite range that the extrema pass folded
+// into its range slots (no finite value: the range is empty and e = 0). Each
+// wave folds the slots by itself, one per lane: no barrier.
+__device__ __forceinline__ uint64_t bound_bits(const FieldC& f) {
   const int rel = f.eb_mode == 1;
-  uint64_t lo = ~0ull, hi = 0;
-  if (rel) {
-    for (uint32_t i = threadIdx.x; i < f.nparts; i += kWG) {
-      const uint64_t a = f.part[2 * i], c = f.part[2 * i + 1];
-      lo = a < lo ? a : lo;
-      hi = c > hi ? c : hi;
-    }
+  uint64_t lo_inv = 0, hi = 0;
+  const uint32_t l = lane_id();
+  if (rel && l < f.nslots) {
+    lo_inv = f.range[l * (kRangeStride / 8)];
+    hi = f.range[l * (kRangeStride / 8) + 1];
   }
-  lo = group_min<kWave, uint64_t>(lo);
+  lo_inv = group_max<kWave, uint64_t>(lo_inv);
   hi = group_max<kWave, uint64_t>(hi);
-  if (lane_id() == 0) {
-    s_lo[threadIdx.x / kWave] = lo;
-    s_hi[threadIdx.x / kWave] = hi;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int i = 0; i < kWavesPerWG; ++i) {
-      lo = s_lo[i] < lo ? s_lo[i] : lo;
-      hi = s_hi[i] > hi ? s_hi[i] : hi;
-    }
-    f.ctr->klo = lo;
-    f.ctr->khi = hi;
-    f.ctr->e_bits = f.dtype == 0 ? (uint64_t)bits_of(bound_from<float>(rel, f.eb, lo, hi))
-                                 : (uint64_t)bits_of(bound_from<double>(rel, f.eb, lo, hi));
-  }
+  const uint64_t lo = ~lo_inv;
+  return f.dtype == 0 ? (uint64_t)bits_of(bound_from<float>(rel, f.eb, lo, hi))
+                      : (uint64_t)bits_of(bound_from<double>(rel, f.eb, lo, hi));
 }
 
 // Parameters of one block from its totalOrder extrema (keys): K = -1 for a
@@ -265,18 +272,27 @@ __device__ __forceinline__ void classify_tile(const FieldC& f, uint32_t t, uint3
   constexpr int BPT = CLS / kWG;  // blocks per thread
   const U* stats = reinterpret_cast<const U*>(f.stats);
   const uint64_t nblk = f.nblk;
-  const T e = from_bits<T>((U)f.ctr->e_bits);
+  const uint64_t k0 = (uint64_t)t * CLS + (uint64_t)threadIdx.x * BPT;
+  U kmin[BPT], kmax[BPT];
+#pragma unroll
+  for (int i = 0; i < BPT; ++i) {
+    const uint64_t k = k0 + i;
+    kmin[i] = k < nblk ? stats[2 * k] : (U)0;
+    kmax[i] = k < nblk ? stats[2 * k + 1] : (U)0;
+  }
+  const uint64_t e_bits = bound_bits(f);
+  const T e = from_bits<T>((U)e_bits);
+  if (t == 0 && threadIdx.x == 0) f.ctr->e_bits = e_bits;  // read by the encode pass and the header
   const uint32_t ntiles = (uint32_t)cdiv(nblk, CLS);
   T* mus = reinterpret_cast<T*>(f.out + f.mu_off);
   for (int i = threadIdx.x; i < CLS / 32; i += kWG) s_state[i] = 0;
   __syncthreads();
-  const uint64_t k0 = (uint64_t)t * CLS + (uint64_t)threadIdx.x * BPT;
   uint32_t cnt = 0, bits = 0;
 #pragma unroll
   for (int i = 0; i < BPT; ++i) {
     const uint64_t k = k0 + i;
     if (k < nblk) {
-      const BlockPlan<T> p = plan_block<T>(stats[2 * k], stats[2 * k + 1], e);
+      const BlockPlan<T> p = plan_block<T>(kmin[i], kmax[i], e);
       mus[k] = p.mu;
       const bool nc = p.K != 0;
       cnt += nc ? 1u : 0u;
@@ -311,7 +327,7 @@ __global__ __launch_bounds__(256) void k_classify(CBatch b) {
   __shared__ uint32_t s_state[CLS / 32 > 32 ? CLS / 32 : 32];
   __shared__ uint64_t s_base;
   const uint64_t g = blockIdx.x;
-  const FieldC& f = field_at(b, field_of(b.field_cls[Traits<T>::BYTES / 8], g));
+  const FieldC f = field_at(b, field_of(b.field_cls[Traits<T>::BYTES / 8], g));
   classify_tile<T, B>(f, (uint32_t)(g - f.base_cls), s_scan, s_state, &s_base);
 }
 
@@ -430,6 +446,8 @@ struct TileIn {
   uint64_t r0;                    // rank of the tile's first non-constant block
   uint32_t field;                 // batch entry
   uint32_t tile;                  // tile within the field
+  T e;                            // the field's bound and non-constant block count,
+  uint64_t n_nc;                  // read with the tile so their latency hides too
 };
 
 // Loads and plans tile t: extrema, plan, ranks within the tile (barriers),
@@ -471,7 +489,7 @@ __device__ __forceinline__ void tile_load(TileIn<T, B>& in, uint32_t t, const T*
 // tickets from the kTicketClasses counters of this type; ticket i of class c
 // is global tile kTicketClasses * i + c, global tiles running over the fields
 // of this type in order.
-template <typename T, int B>
+template <typename T, int B, int BATCH>
 __device__ __forceinline__ void encode_pass(const CBatch& b, uint32_t* s_scan, uint32_t* s_tile, uint64_t* s_base,
                                             uint32_t* s_stage) {
   using U = typename Traits<T>::U;
@@ -494,12 +512,14 @@ __device__ __forceinline__ void encode_pass(const CBatch& b, uint32_t* s_scan, u
     return v;
   };
   auto load = [&](TileIn<T, B>& in, uint64_t gt) {
-    const uint32_t fi = field_of(b.field_enc[DT], gt);
-    const FieldC& f = field_at(b, fi);
+    const uint32_t fi = field_of<BATCH>(b.field_enc[DT], gt);
+    const FieldC f = field_at<BATCH>(b, fi);
     in.field = fi;
     in.tile = (uint32_t)(gt - f.base_enc);
+    in.e = from_bits<T>((U)f.ctr->e_bits);
+    in.n_nc = f.ctr->n_nc;
     tile_load<T, B>(in, in.tile, reinterpret_cast<const T*>(f.in), reinterpret_cast<const U*>(f.stats), f.enc_r0,
-                    f.n, f.nblk, from_bits<T>((U)f.ctr->e_bits), s_scan);
+                    f.n, f.nblk, in.e, s_scan);
   };
 
   for (int i = threadIdx.x; i < STAGE_WORDS / 4; i += kWG)
@@ -510,10 +530,10 @@ __device__ __forceinline__ void encode_pass(const CBatch& b, uint32_t* s_scan, u
   load(cur, gt);
 
   for (;;) {
-    const FieldC& f = field_at(b, cur.field);
+    const FieldC f = field_at<BATCH>(b, cur.field);
     const uint32_t t = cur.tile;
-    const T e = from_bits<T>((U)f.ctr->e_bits);
-    const Sections sec = sections(f.nblk, f.ctr->n_nc, BYTES, B, 0);
+    const T e = cur.e;
+    const Sections sec = sections(f.nblk, cur.n_nc, BYTES, B, 0);
     uint8_t* out = f.out;
     T* mus = reinterpret_cast<T*>(out + f.mu_off);
     uint64_t* mid_status = f.enc_mid;
@@ -593,15 +613,14 @@ __device__ __forceinline__ void encode_pass(const CBatch& b, uint32_t* s_scan, u
     gt = claim();  // its barriers also order the staging before the copy-out
     const bool more = gt < ntiles;
     if (more) load(cur, gt);
-    const FieldC& fc = field_at(b, f_cur);
+    const FieldC fc = field_at<BATCH>(b, f_cur);
     if (threadIdx.x < kWave) {
       const uint64_t p = lookback_resolve(fc.enc_mid, t_cur, tile_bytes, &fc.ctr->err, 1u);
       if (threadIdx.x == 0) *s_base = p;
     }
     __syncthreads();
     const uint64_t base = *s_base;
-    const Sections secc = sections(fc.nblk, fc.ctr->n_nc, BYTES, B, 0);
-    copy_out(fc.out, secc.mid + base, s_stage, tile_bytes);
+    copy_out(fc.out, sec.mid + base, s_stage, tile_bytes);
     if (t_cur == cdiv(fc.nblk, G::TBLK) - 1 && threadIdx.x == 0) fc.ctr->mid_total = base + tile_bytes;
     __syncthreads();
     for (int i = threadIdx.x; i < STAGE_WORDS / 4; i += kWG)
@@ -610,22 +629,23 @@ __device__ __forceinline__ void encode_pass(const CBatch& b, uint32_t* s_scan, u
   }
 }
 
-template <typename T, int B>
-__global__ __launch_bounds__(256) void k_encode(CBatch b) {
+template <typename T, int B, int BATCH>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_encode(CBatch b) {
   using G = Geo<T, B>;
   __shared__ uint32_t s_scan[G::SUB * kWavesPerWG];
   __shared__ uint32_t s_tile;
   __shared__ uint64_t s_base;
   __shared__ __align__(16) uint32_t s_stage[(G::TILE * G::SUB * Traits<T>::BYTES + 16) / 4 + 8];
-  encode_pass<T, B>(b, s_scan, &s_tile, &s_base, s_stage);
+  encode_pass<T, B, BATCH>(b, s_scan, &s_tile, &s_base, s_stage);
 }
 
 // --------------------------------------------------------------- finalize ---
 
 // Header, section padding and stream size; one workgroup a field.
 __global__ void k_finalize(CBatch b) {
-  const FieldC& f = field_at(b, blockIdx.x);
+  const FieldC f = field_at(b, blockIdx.x);
   const Counters* ctr = f.ctr;
+  const uint64_t e_bits = bound_bits(f);
   const uint32_t w = f.dtype == 0 ? 4 : 8;
   const uint64_t n_nc = ctr->n_nc, mid_total = ctr->mid_total;
   const Sections s = sections(f.nblk, n_nc, w, f.b, mid_total);
@@ -640,7 +660,7 @@ __global__ void k_finalize(CBatch b) {
     for (int d = 0; d < 4; ++d) o64[2 + d] = f.dims[d];
     o64[6] = f.n;
     o64[7] = (uint64_t)__double_as_longlong(f.eb);
-    o64[8] = ctr->e_bits;
+    o64[8] = e_bits;
     o64[9] = f.nblk;
     o64[10] = n_nc;
     o64[11] = mid_total;
@@ -669,16 +689,23 @@ hipError_t launch_compress_b(const CBatch& b, const CLaunchGeom& g, hipStream_t 
   if (b.tiles_stats[0] + b.tiles_stats[1] > 0) {
     if (b.tiles_stats[0]) run("k_stats", [&] { k_stats<float, B><<<(uint32_t)b.tiles_stats[0], 256, 0, stream>>>(b); });
     if (b.tiles_stats[1]) run("k_stats", [&] { k_stats<double, B><<<(uint32_t)b.tiles_stats[1], 256, 0, stream>>>(b); });
-    run("k_range", [&] { k_range<<<b.nfields, 256, 0, stream>>>(b); });
     if (b.tiles_cls[0]) run("k_classify", [&] { k_classify<float, B><<<(uint32_t)b.tiles_cls[0], 256, 0, stream>>>(b); });
     if (b.tiles_cls[1]) run("k_classify", [&] { k_classify<double, B><<<(uint32_t)b.tiles_cls[1], 256, 0, stream>>>(b); });
     for (int dt = 0; dt < 2; ++dt) {
       if (!b.tiles_enc[dt]) continue;
-      const uint32_t genc = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(b.tiles_enc[dt], g.encode_wgs));
-      if (dt == 0)
-        run("k_encode", [&] { k_encode<float, B><<<genc, 256, 0, stream>>>(b); });
+      // at least one workgroup per ticket class: tiles of a class without one
+      // would never be encoded (and every later tile would wait for them)
+      const uint64_t want = std::max<uint64_t>(g.encode_wgs[dt], kTicketClasses);
+      const uint32_t genc = (uint32_t)std::min<uint64_t>(b.tiles_enc[dt], want);
+      const bool batch = b.fields != nullptr;
+      if (dt == 0 && !batch)
+        run("k_encode", [&] { k_encode<float, B, kSingle><<<genc, 256, 0, stream>>>(b); });
+      else if (dt == 0)
+        run("k_encode", [&] { k_encode<float, B, kBatch><<<genc, 256, 0, stream>>>(b); });
+      else if (!batch)
+        run("k_encode", [&] { k_encode<double, B, kSingle><<<genc, 256, 0, stream>>>(b); });
       else
-        run("k_encode", [&] { k_encode<double, B><<<genc, 256, 0, stream>>>(b); });
+        run("k_encode", [&] { k_encode<double, B, kBatch><<<genc, 256, 0, stream>>>(b); });
     }
   }
   run("k_finalize", [&] { k_finalize<<<b.nfields, 64, 0, stream>>>(b); });

@@ -28,8 +28,17 @@ namespace szx {
 constexpr uint32_t kStatusCorrupt = 3;  // SZ_ECORRUPT
 constexpr uint32_t kStatusDevice = 4;   // SZ_EDEVICE: a bounded wait gave up
 
-__device__ __forceinline__ const FieldD& field_at(const DBatch& b, uint32_t f) {
-  return b.fields ? b.fields[f] : b.one;
+// Field of a call, or of a batch entry (a copy with its pointers typed as
+// global memory).
+__device__ __forceinline__ FieldD field_at(const DBatch& b, uint32_t fi) {
+  FieldD f = b.fields ? b.fields[fi] : b.one;
+  f.in = as_global(f.in);
+  f.out = as_global(f.out);
+  f.status = as_global(f.status);
+  f.index = as_global(f.index);
+  f.rank_st = as_global(f.rank_st);
+  f.mid_st = as_global(f.mid_st);
+  return f;
 }
 __device__ __forceinline__ uint32_t dfield_of(const uint32_t* map, uint64_t t) { return map ? map[t] : 0u; }
 
@@ -274,7 +283,7 @@ __global__ __launch_bounds__(256) void k_dindex(DBatch b) {
   __shared__ uint32_t s_scan[kWavesPerWG];
   __shared__ uint64_t s_r0, s_m0;
   const uint64_t g = blockIdx.x;
-  const FieldD& f = field_at(b, dfield_of(b.field_idx[Traits<T>::BYTES / 8], g));
+  const FieldD f = field_at(b, dfield_of(b.field_idx[Traits<T>::BYTES / 8], g));
   dindex_tile<T, B>(f, (uint32_t)(g - f.base_idx), s_scan, &s_r0, &s_m0);
 }
 
@@ -457,7 +466,7 @@ __global__ __launch_bounds__(256) void k_decode(DBatch b) {
   __shared__ uint32_t s_scan[G::SUB * kWavesPerWG];
   __shared__ __align__(16) uint32_t s_stage[(G::TILE * G::SUB * Traits<T>::BYTES + 32) / 4 + 8];
   const uint64_t g = blockIdx.x;
-  const FieldD& f = field_at(b, dfield_of(b.field_dec[Traits<T>::BYTES / 8], g));
+  const FieldD f = field_at(b, dfield_of(b.field_dec[Traits<T>::BYTES / 8], g));
   decode_tile<T, B>(f, (uint32_t)(g - f.base_dec), s_scan, s_stage);
 }
 

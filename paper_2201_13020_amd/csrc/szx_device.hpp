@@ -12,6 +12,17 @@
 
 namespace szx {
 
+// A pointer read from a field descriptor in memory is typed generic, so every
+// access through it would compile to flat instructions (which wait on both
+// the vector-memory and the LDS counters). Descriptors only hold device
+// memory: re-read the pointer's bits as a global-memory pointer, so that the
+// compiler infers global accesses through it.
+template <typename P>
+__device__ __forceinline__ P as_global(const P& member) {
+  const uint64_t raw = *reinterpret_cast<const uint64_t*>(&member);
+  return (P)(__attribute__((address_space(1))) char*)raw;
+}
+
 constexpr int kWave = 64;
 constexpr int kWG = 256;
 constexpr int kWavesPerWG = kWG / kWave;

@@ -20,13 +20,13 @@ struct FieldC {
   uint64_t dims[4];
   double eb;
   uint32_t dtype, eb_mode, ndims, b;
+  uint32_t nslots, pad;
   Counters* ctr;
+  uint64_t* range;      // range slots: slot i at range + i * kRangeStride / 8 (lo_inv, hi)
   void* stats;          // two totalOrder keys per block
-  uint64_t* part;       // finite range per chunk of the extrema pass
   uint64_t* enc_r0;     // first rank of every encode tile
   uint64_t* cls_status; // scan status words, classification tiles
   uint64_t* enc_mid;    // scan status words, encode tiles
-  uint32_t nparts, pad;
   uint64_t base_stats, base_cls, base_enc;  // first chunk / tile of the field in its type's numbering
 };
 
@@ -51,7 +51,7 @@ struct CBatch {
 
 // Launch geometry (no effect on the output bytes).
 struct CLaunchGeom {
-  uint32_t encode_wgs;  // persistent workgroups of the encode pass
+  uint32_t encode_wgs[2];  // persistent workgroups of the encode pass, per element type
 };
 
 // One field of a decompression.

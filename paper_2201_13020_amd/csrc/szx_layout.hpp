@@ -32,7 +32,7 @@ __host__ __device__ inline Sections sections(uint64_t nblk, uint64_t n_nc, uint6
 struct Counters {
   uint32_t err;        // nonzero: a bounded wait of the compression gave up
   uint32_t reserved[3];
-  uint64_t klo, khi;   // totalOrder keys of the smallest / largest finite value
+  uint64_t reserved2[2];
   uint64_t n_nc;       // non-constant blocks (raw included)
   uint64_t mid_total;  // mid-byte section size
   uint64_t e_bits;     // bit pattern of the bound e in the element type
@@ -71,6 +71,18 @@ constexpr uint32_t kTicketClasses = 8;
 // Tiles of the extrema pass per chunk; a chunk leaves one finite range.
 constexpr uint32_t kStatsChunk = 8;
 
+// The extrema pass folds each chunk's finite range into one of a field's
+// range slots (chunk c into slot c mod slots), by 64-bit atomic maxima of
+// the complemented smallest key and of the largest key, so that a cleared
+// slot is the identity. Device-scope atomics on one address serialise
+// (tens of ns each across XCDs), so the slots sit kRangeStride bytes apart;
+// readers fold at most kRangeSlots slots, one per lane of a wave.
+constexpr uint32_t kRangeSlots = 64;
+constexpr uint32_t kRangeStride = 256;
+__host__ __device__ inline uint32_t range_slots(uint64_t chunks) {
+  return (uint32_t)(chunks < kRangeSlots ? (chunks ? chunks : 1) : kRangeSlots);
+}
+
 // Values per row of a tile for block size b (mirrors Geo::TILE).
 __host__ __device__ inline uint64_t row_values(uint32_t b) { return 256ull * (b >= 512 ? b / 64 : 8); }
 
@@ -92,22 +104,22 @@ __host__ __device__ inline FieldTiles field_tiles(uint64_t n, uint64_t nblk, uin
 // Workspace of one field: a cleared region first (counters, tickets, scan
 // status words), then the rest; every piece 256-byte aligned.
 struct WsLayout {
-  uint64_t counters, tickets, cls_status, enc_mid, dec_rank, dec_mid, zero_end;
-  uint64_t part, stats, enc_r0, dec_index, total;
+  uint64_t counters, range, tickets, cls_status, enc_mid, dec_rank, dec_mid, zero_end;
+  uint64_t stats, enc_r0, dec_index, total;
 };
 
 __host__ __device__ inline WsLayout ws_layout(uint64_t n, uint64_t nblk, uint32_t w, uint32_t b) {
   const FieldTiles ft = field_tiles(n, nblk, w, b);
   WsLayout L;
   L.counters = 0;
-  L.tickets = 256;
+  L.range = 256;
+  L.tickets = L.range + (uint64_t)range_slots(ft.chunks) * kRangeStride;
   L.cls_status = align256(L.tickets + 2ull * kTicketClasses * 256);
   L.enc_mid = align256(L.cls_status + (ft.cls + 1) * 8);
   L.dec_rank = align256(L.enc_mid + (ft.enc + 1) * 8);
   L.dec_mid = align256(L.dec_rank + (ft.cls + 1) * 8);
   L.zero_end = align256(L.dec_mid + (ft.cls + 1) * 8);
-  L.part = L.zero_end;
-  L.stats = align256(L.part + (ft.chunks + 1) * 16);
+  L.stats = L.zero_end;
   L.enc_r0 = align256(L.stats + nblk * 2 * (uint64_t)w);
   L.dec_index = align256(L.enc_r0 + (ft.enc + 1) * 8);
   L.total = align256(L.dec_index + (ft.enc + 1) * 16);

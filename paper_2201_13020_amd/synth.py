@@ -45,7 +45,7 @@ def _spectral_field(shape, r, slope):
         amp = np.where(k2 > 0, k2 ** (slope / 2.0), 0.0)
     F *= amp
     del amp, k2
-    x = np.fft.irfftn(F, s=shape)
+    x = np.fft.irfftn(F, s=shape, axes=tuple(range(len(shape))))
     x -= x.mean()
     sd = x.std()
     if sd > 0:
@@ -159,9 +159,9 @@ def make(name, shape=None, field=0):
 # each field's values come from torch's generator seeded with 13020 + 6000 +
 # index, on whatever device the caller names (the full batch is several GiB,
 # so it is generated where it is used). The content follows the generators
-# above: 1-D fields are sums of sines with noise, 2-D and 3-D fields are
-# Gaussian random fields with a k^(-5/3) energy spectrum, half of them with
-# exact-zero regions.
+# above: 1-D fields are sums of sines with noise, 2-D and 3-D fields are cut
+# from periodic Gaussian random fields with a k^(-5/3) energy spectrum, half
+# of them with exact-zero regions.
 
 _BATCH_CFG = 6
 
@@ -225,13 +225,37 @@ def _torch_spectral(shape, g, slope, device):
     return x
 
 
+_MOTHERS = {}
+
+
+def _mothers(device):
+    """Periodic Gaussian random fields (k^(-5/3) energy spectrum) in 2-D and
+    3-D, with smoother fields (|k|^-3) whose global 20 % quantile marks the
+    zero regions; generated once per device. Batch fields of 2 and 3 dims are
+    cut from them at seeded offsets, indices wrapping around (the fields are
+    periodic), so no field needs an FFT of its own."""
+    import torch
+    key = str(device)
+    if key not in _MOTHERS:
+        big = torch.device(device).type == "cuda"
+        g = torch.Generator(device=device)
+        g.manual_seed(13020 + 1000 * _BATCH_CFG + 999_999)
+        out = {}
+        for nd, shape in ((2, (4096, 4096) if big else (512, 512)), (3, (384, 384, 384) if big else (64, 64, 64))):
+            x = _torch_spectral(shape, g, -11.0 / 6.0, device)
+            m = _torch_spectral(shape, g, -3.0, device)
+            flat = m.reshape(-1)
+            step = max(1, flat.numel() // (1 << 20))
+            thr = torch.quantile(flat[::step], 0.2)
+            out[nd] = (x, m < thr)
+        _MOTHERS[key] = out
+    return _MOTHERS[key]
+
+
 def batch_field(spec, device="cpu"):
     """Values of one batch field as a contiguous torch tensor of the spec's
     dims and element type on `device`."""
     import torch
-    if torch.device(device).type == "cuda":
-        # thousands of distinct shapes: keep few FFT plans (and their workspaces)
-        torch.backends.cuda.cufft_plan_cache[torch.device(device).index or 0].max_size = 8
     g = torch.Generator(device=device)
     g.manual_seed(spec["seed"])
     dims = tuple(int(d) for d in spec["dims"])
@@ -246,15 +270,20 @@ def batch_field(spec, device="cpu"):
         for j in range(8):
             x += torch.sin(2 * np.pi * f[j] * t + ph[j])
         x += 1e-3 * torch.randn(n, generator=g, device=device, dtype=torch.float64)
-    else:
-        x = _torch_spectral(dims, g, -11.0 / 6.0, device)
-        if spec["zero_regions"]:
-            m = _torch_spectral(dims, g, -3.0, device)
-            flat = m.reshape(-1)
-            step = max(1, flat.numel() // (1 << 20))
-            thr = torch.quantile(flat[::step], 0.2)
-            x[m < thr] = 0.0
-    return x.to(dt).contiguous()
+        return x.to(dt).contiguous()
+    mother, zmask = _mothers(device)[len(dims)]
+    u = torch.rand(len(dims), generator=g, device=device, dtype=torch.float64).cpu()
+    idx = []
+    for ax, d in enumerate(dims):
+        M = mother.shape[ax]
+        o = int(u[ax] * M)
+        view = [1] * len(dims)
+        view[ax] = d
+        idx.append(((torch.arange(d, device=device) + o) % M).view(view))
+    x = mother[tuple(idx)].to(dt)
+    if spec["zero_regions"]:
+        x[zmask[tuple(idx)]] = 0.0
+    return x.contiguous()
 
 
 # ----------------------------------------------------------- serving traces --

@@ -82,14 +82,36 @@ def lib():
         L.sz_batch_create_compress.restype = ctypes.c_int
         L.sz_batch_create_decompress.argtypes = [DF, ctypes.c_uint32, vp, u64, ctypes.POINTER(vp)]
         L.sz_batch_create_decompress.restype = ctypes.c_int
-        L.sz_batch_set_geometry.argtypes = [vp, ctypes.c_uint32]
+        L.sz_batch_set_geometry.argtypes = [vp, ctypes.c_uint32, ctypes.c_uint32]
         L.sz_batch_set_geometry.restype = ctypes.c_int
+        L.sz_size_class.argtypes = [u64]
+        L.sz_size_class.restype = ctypes.c_uint32
+        L.sz_set_geometry.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32]
+        L.sz_set_geometry.restype = ctypes.c_int
         L.sz_batch_run.argtypes = [vp, vp]
         L.sz_batch_run.restype = ctypes.c_int
         L.sz_batch_destroy.argtypes = [vp]
         L.sz_batch_destroy.restype = None
         _lib = L
     return _lib
+
+
+def _dtype_code(dtype):
+    if dtype in (torch.float32, "float32", "f32", SZ_F32):
+        return SZ_F32
+    if dtype in (torch.float64, "float64", "f64", SZ_F64):
+        return SZ_F64
+    raise ValueError(f"unsupported dtype {dtype}")
+
+
+def size_class(nbytes):
+    return int(lib().sz_size_class(int(nbytes)))
+
+
+def set_geometry(dtype, size_class, encode_wgs):
+    """Process-wide encode geometry for one element type and size class
+    (0 restores the default)."""
+    _check(lib().sz_set_geometry(_dtype_code(dtype), int(size_class), int(encode_wgs)), "sz_set_geometry")
 
 
 def _check(rc, what):
@@ -246,8 +268,10 @@ class Batch:
     def run(self, stream=None):
         _check(lib().sz_batch_run(self._h, _stream_handle(stream)), "sz_batch_run")
 
-    def set_geometry(self, encode_wgs):
-        _check(lib().sz_batch_set_geometry(self._h, int(encode_wgs)), "sz_batch_set_geometry")
+    def set_geometry(self, encode_wgs, dtype=None):
+        """Encode workgroups for the fields of one element type (both if None)."""
+        for dt in ([SZ_F32, SZ_F64] if dtype is None else [_dtype_code(dtype)]):
+            _check(lib().sz_batch_set_geometry(self._h, dt, int(encode_wgs)), "sz_batch_set_geometry")
 
     def close(self):
         if self._h:

@@ -8,11 +8,11 @@ import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "szx.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("szx.h", "szx_server.h")]
 
 
 def declared_functions():
-    text = open(HEADER).read()
+    text = "".join(open(h).read() for h in HEADERS)
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     names = re.findall(r"\b(sz_[a-z_]+)\s*\(", text)
     return sorted(set(names))
@@ -73,3 +73,61 @@ def test_argument_errors_are_returned_without_a_device():
     assert b"null" in L.sz_last_error()
     p.block_size = 12
     assert L.sz_compress(ctypes.byref(p), None, None, 0, None, None, 0, None) == 1
+
+
+def test_size_classes_and_geometry_table():
+    from paper_2201_13020_amd import szx
+    K = 1 << 10
+    cases = [(0, 0), (256 * K - 1, 0), (256 * K, 1), (1 << 20, 2), (4 << 20, 3), (16 << 20, 4),
+             (64 << 20, 5), (256 << 20, 6), (1 << 30, 7), (1 << 40, 7)]
+    for nbytes, c in cases:
+        assert szx.size_class(nbytes) == c, nbytes
+    szx.set_geometry("f32", 3, 512)
+    szx.set_geometry("f32", 3, 0)  # back to the default
+    with pytest.raises(szx.SzError):
+        szx.set_geometry("f64", 8, 1)
+    L = szx.lib()
+    assert L.sz_batch_set_geometry(None, 0, 64) == 1  # SZ_EINVAL
+    assert L.sz_batch_run(None, None) == 1
+
+
+def test_batch_planning_errors_without_a_device():
+    """Batch sizing is host-only: mixed block sizes, an empty batch, both or
+    neither of the field kinds give 0."""
+    from paper_2201_13020_amd import szx
+    import torch
+    L = szx.lib()
+    arr = (szx.SzCField * 2)()
+    arr[0].params = szx.make_params(torch.float32, (1000,), 1e-3, "rel", 128)
+    arr[1].params = szx.make_params(torch.float64, (77, 3), 1e-3, "abs", 128)
+    one = int(L.sz_batch_workspace_size(arr, None, 2))
+    assert one > 0
+    assert L.sz_batch_workspace_size(arr, None, 0) == 0
+    darr = (szx.SzDField * 1)()
+    darr[0].expected = arr[0].params
+    assert L.sz_batch_workspace_size(arr, darr, 1) == 0
+    assert L.sz_batch_workspace_size(None, None, 1) == 0
+    assert L.sz_batch_workspace_size(None, darr, 1) > 0
+    arr[1].params = szx.make_params(torch.float64, (77, 3), 1e-3, "abs", 64)
+    assert L.sz_batch_workspace_size(arr, None, 2) == 0
+
+
+def test_server_entry_points_fail_cleanly_without_a_device():
+    """Creating a server needs a device; without one the error comes back as
+    SZ_EDEVICE and the other entry points reject a null server."""
+    from paper_2201_13020_amd import serve, szx
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    with pytest.raises(szx.SzError) as e:
+        serve.Server(hbm_budget=1 << 30)
+    assert e.value.code == 4
+    L = serve._lib()
+    rid = ctypes.c_uint64()
+    p = szx.make_params(torch.float32, (100,), 1e-3, "rel", 128)
+    assert L.sz_server_submit_compress(None, ctypes.byref(p), None, 0, ctypes.byref(rid)) == 1
+    assert L.sz_server_poll(None, None, 0, 0) == 0
+    assert L.sz_server_release(None, 1) == 1
+    cfg = serve.SzServerConfig(device=0, hbm_budget=1 << 30, slots=0, max_batch=1, block_size=128)
+    h = ctypes.c_void_p()
+    assert L.sz_server_create(ctypes.byref(cfg), ctypes.byref(h)) == 1  # slots out of range

@@ -1,0 +1,167 @@
+"""Serving runtime: every result in a mix of overlapping requests equals the
+result of that request alone (and the oracle's), admission keeps to the HBM
+budget, items outlive their readers."""
+import time
+
+import numpy as np
+import pytest
+
+from oracle import szref
+from gpu_util import same_bits
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _fields(count, seed):
+    from paper_2201_13020_amd import synth
+    specs = synth.batch_specs(count, median=256 << 10, hi=8 << 20, seed_cfg=60 + seed)
+    return specs, [synth.batch_field(sp, "cuda") for sp in specs]
+
+
+def _drain(srv, n, timeout=120.0):
+    out = []
+    t_end = time.time() + timeout
+    while len(out) < n and time.time() < t_end:
+        out += srv.poll(20_000)
+    assert len(out) == n, f"{len(out)} of {n} completions"
+    return out
+
+
+def test_results_identical_alone_and_in_mix():
+    from paper_2201_13020_amd import serve, szx
+    specs, xs = _fields(48, 1)
+    # alone: the plain single-field path, one call at a time
+    alone_streams, alone_values = [], []
+    for sp, x in zip(specs, xs):
+        o, s = szx.compress(x, sp["eb"], "rel", 128, dims=sp["dims"])
+        torch.cuda.synchronize()
+        n = int(s.cpu().view(torch.int64).item())
+        alone_streams.append(o[:n].clone())
+        y, st = szx.decompress(o, n, dict(dtype=x.dtype, dims=sp["dims"], block=128))
+        torch.cuda.synchronize()
+        assert int(st.cpu().view(torch.int32).item()) == 0
+        alone_values.append(y.clone())
+    # the alone results are the oracle's
+    for i in (0, 7, 19, 33):
+        xh = xs[i].cpu().numpy()
+        assert np.array_equal(alone_streams[i].cpu().numpy(), szref.compress(xh, specs[i]["eb"], "rel", 128))
+
+    with serve.Server(hbm_budget=2 << 30, slots=4, max_batch=8) as srv:
+        # first wave: all compressions at once
+        req = {srv.submit_compress(x, sp["eb"], dims=sp["dims"]): i for i, (sp, x) in enumerate(zip(specs, xs))}
+        items = {}
+        for c in _drain(srv, len(xs)):
+            assert c["status"] == 0
+            items[req[c["request"]]] = c["item"]
+        # second wave: decompressions of every item (half into caller buffers,
+        # half into the arena) interleaved with compressions of the same fields again
+        outs = {}
+        req2 = {}
+        for i in range(len(xs)):
+            if i % 2 == 0:
+                outs[i] = torch.zeros_like(alone_values[i])
+                req2[srv.submit_decompress(items[i], out=outs[i])] = ("d", i)
+            else:
+                req2[srv.submit_decompress(items[i])] = ("d", i)
+            req2[srv.submit_compress(xs[i], specs[i]["eb"], dims=specs[i]["dims"])] = ("c", i)
+        comps = _drain(srv, len(req2))
+        groups = [c["group_size"] for c in comps]
+        assert max(groups) > 1, "requests were never grouped"
+        for c in comps:
+            kind, i = req2[c["request"]]
+            assert c["status"] == 0, (kind, i)
+            if kind == "c":
+                got = srv.read_item(c["item"])
+                assert torch.equal(got, alone_streams[i]), f"stream {i} differs in the mix"
+                srv.release(c["item"])
+            else:
+                if c["out_item"]:
+                    y = srv.read_item(c["out_item"])
+                    srv.release(c["out_item"])
+                else:
+                    y = outs[i].view(torch.uint8).reshape(-1)
+                ref = alone_values[i].view(torch.uint8).reshape(-1)
+                assert torch.equal(y[: ref.numel()], ref), f"values {i} differ in the mix"
+        for i in range(len(xs)):
+            got = srv.read_item(items[i])
+            assert torch.equal(got, alone_streams[i])
+        st = srv.stats()
+        assert st["arena_peak"] <= st["arena_bytes"]
+
+
+def test_admission_keeps_to_the_budget():
+    """Forty 8 MiB compressions into a 48 MiB arena: they queue, run in
+    turn, all succeed, and the arena never overflows; a request that could
+    never fit completes with SZ_ENOMEM."""
+    from paper_2201_13020_amd import serve, synth, szx
+    x = synth.batch_field(dict(dims=(2 << 20,), dtype="float32", eb=1e-3, zero_regions=False, seed=5), "cuda")
+    with serve.Server(hbm_budget=48 << 20, slots=3, max_batch=16) as srv:
+        reqs = [srv.submit_compress(x, 1e-3) for _ in range(40)]
+        big = torch.zeros(16 << 20, dtype=torch.float32, device="cuda")
+        r_big = srv.submit_compress(big, 1e-3)
+        # resident streams hold arena bytes until released: release each as it
+        # completes, so the queued requests can be admitted
+        by = {}
+        t_end = time.time() + 120
+        while len(by) < 41 and time.time() < t_end:
+            for c in srv.poll(20_000):
+                by[c["request"]] = c
+                if c["status"] == 0:
+                    srv.release(c["item"])
+        assert len(by) == 41, f"{len(by)} of 41 completions"
+        assert by[r_big]["status"] == 5  # SZ_ENOMEM
+        sizes = set()
+        for r in reqs:
+            assert by[r]["status"] == 0
+            sizes.add(by[r]["stream_bytes"])
+        assert len(sizes) == 1
+        st = srv.stats()
+        assert st["arena_peak"] <= st["arena_bytes"] and st["arena_in_use"] == 0
+        assert st["groups_launched"] >= 4  # could not all run at once
+
+
+def test_release_waits_for_readers_and_errors():
+    from paper_2201_13020_amd import serve, synth, szx
+    x = synth.batch_field(dict(dims=(300_000,), dtype="float64", eb=1e-4, zero_regions=False, seed=9), "cuda")
+    with serve.Server(hbm_budget=256 << 20, slots=2, max_batch=4) as srv:
+        r = srv.submit_compress(x, 1e-4)
+        (c,) = _drain(srv, 1)
+        item = c["item"]
+        y = torch.empty_like(x)
+        rd = srv.submit_decompress(item, out=y)
+        srv.release(item)  # deferred: a decompression is queued on it
+        (d,) = _drain(srv, 1)
+        assert d["request"] == rd and d["status"] == 0
+        ref = szref.decompress(szref.compress(x.cpu().numpy(), 1e-4, "rel", 128))
+        assert same_bits(y.cpu().numpy(), ref)
+        with pytest.raises(szx.SzError):
+            srv.submit_decompress(item)  # gone now
+        with pytest.raises(szx.SzError):
+            srv.submit_compress(x, 1e-4, params=szx.make_params(x.dtype, x.shape, 1e-4, "rel", 64))
+        assert srv.stats()["items_resident"] == 0
+
+
+def test_trace_replay_small():
+    """A short Poisson trace through the load driver: every request
+    completes, and the summary is consistent."""
+    from paper_2201_13020_amd import serve, synth
+    bases = {False: synth.batch_field(dict(dims=(8 << 20,), dtype="float32", eb=1e-3, zero_regions=False,
+                                           seed=21), "cuda"),
+             True: synth.batch_field(dict(dims=(4 << 20,), dtype="float64", eb=1e-3, zero_regions=False,
+                                          seed=22), "cuda")}
+    warm = synth.serve_trace(16, 0.0, seed=1, hi=4 << 20)
+    warm["kind"][:] = 0
+    trace = synth.serve_trace(200, 2000.0, seed=2, hi=16 << 20)
+    with serve.Server(hbm_budget=2 << 30, slots=4, max_batch=16) as srv:
+        _, pool = serve.replay(srv, warm, bases)
+        done, pool = serve.replay(srv, trace, bases, warm_items=pool)
+        s = serve.summarize(done)
+        assert s["failed"] == 0 and s["requests"] == len(done) > 150
+        assert 0 < s["p50_ms"] <= s["p99_ms"]
