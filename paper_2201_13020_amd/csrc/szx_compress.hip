@@ -342,52 +342,43 @@ __device__ __forceinline__ bool encode_try(const T (&x)[EPL], int cnt, T mu, T e
   using U = typename Traits<T>::U;
   const int s = shift_of(K);
   const U keep = top_bytes_mask<U>(bytes_of(K));
-  bool ok = true;
 #pragma unroll
-  for (int i = 0; i < EPL; ++i) {
-    const T v = x[i] - mu;
-    const U qi = (U)(bits_of(v) >> s) & keep;
-    q[i] = qi;
-    if (verify) {
-      const T xr = mu + from_bits<T>((U)(qi << s));
-      const bool good = exact_le<T>(x[i], xr, e) && exact_le<T>(xr, x[i], e);
-      ok = ok && (good || i >= cnt);
+  for (int i = 0; i < EPL; ++i) q[i] = (U)(bits_of(x[i] - mu) >> s) & keep;
+  bool ok = true;
+  if (verify) {  // one branch per row, none per value
+#pragma unroll
+    for (int i = 0; i < EPL; ++i) {
+      const T xr = mu + from_bits<T>((U)(q[i] << s));
+      const bool good = exact_le<T>(x[i], xr, e) & exact_le<T>(xr, x[i], e);
+      ok = ok & (good | (i >= cnt));
+      // one value at a time: interleaving all of them costs registers, and
+      // this path is rare
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
   return ok;
 }
 
-template <typename U>
-__device__ __forceinline__ U low_bytes_mask(int L) {
-  return L >= (int)sizeof(U) ? (U)~(U)0 : (U)(((U)1 << (8 * L)) - 1);
-}
-
-// Appends byte strings to a lane's run of the LDS byte stream. Whole dwords
-// the lane owns are written plainly; the first and last, which it may share
-// with its neighbours, are OR-ed into a zeroed stream.
+// Appends byte strings to a lane's run of the LDS byte stream. The stream is
+// zeroed beforehand and every full dword is OR-ed in (the first and last may
+// be shared with the neighbouring lanes), so the only per-value branch is the
+// predicated store itself.
 struct LanePacker {
   uint32_t* stage;
   uint32_t d;     // dword being filled
   uint64_t acc;   // pending bytes, the next byte of the stream in the low byte
   uint32_t fill;  // pending bits
-  bool first;
   __device__ __forceinline__ LanePacker(uint32_t* st, uint32_t off)
-      : stage(st), d(off >> 2), acc(0), fill((off & 3u) * 8u), first(true) {}
-  // L <= 4 bytes of sv, first byte in the low byte
+      : stage(st), d(off >> 2), acc(0), fill((off & 3u) * 8u) {}
+  // L <= 4 bytes of sv, first byte in the low byte, bytes above L zero
   __device__ __forceinline__ void put4(uint32_t sv, int L) {
     acc |= (uint64_t)sv << fill;
     fill += 8u * (uint32_t)L;
-    if (fill >= 32) {
-      const uint32_t w = (uint32_t)acc;
-      if (first)
-        atomicOr(stage + d, w);
-      else
-        stage[d] = w;
-      first = false;
-      ++d;
-      acc >>= 32;
-      fill -= 32;
-    }
+    const bool full = fill >= 32;
+    if (full) atomicOr(stage + d, (uint32_t)acc);
+    d += full ? 1u : 0u;
+    acc = full ? (acc >> 32) : acc;
+    fill = full ? fill - 32u : fill;
   }
   __device__ __forceinline__ void put(uint32_t sv, int L) { put4(sv, L); }
   __device__ __forceinline__ void put(uint64_t sv, int L) {
@@ -561,19 +552,24 @@ __device__ __forceinline__ void encode_pass(const CBatch& b, uint32_t* s_scan, u
         for (int i = 0; i < EPL; ++i) q[i] = bits_of(cur.x[s][i]);
       }
       const int nb = raw ? BYTES : (K > 0 ? bytes_of(K) : 0);
-      U prev = __shfl_up(q[EPL - 1], 1, LPB);
+      U prev = lane_before<LPB, U>(q[EPL - 1]);
       prev = lig == 0 ? (U)0 : prev;
-      uint32_t codes = 0, lb = 0;
+      const int cnt_s = cur.cnt[s];
+      const uint32_t cap = (uint32_t)(nb < 3 ? nb : 3);
+      uint32_t codes = 0, csum = 0;
 #pragma unroll
       for (int i = 0; i < EPL; ++i) {
-        int ci = same_lead_bytes(q[i], prev);
-        ci = ci > 3 ? 3 : ci;
-        ci = ci > nb ? nb : ci;
-        ci = (K > 0 && i < cur.cnt[s]) ? ci : 0;
-        codes |= (uint32_t)ci << (2 * (EPL - 1 - i));
+        // leading identical bytes capped at min(3, nb); a zero difference
+        // counts all bytes, which the cap turns into min(3, nb) as well
+        const uint32_t lz = lead_zero_bits(q[i] ^ prev);
+        uint32_t ci = (lz < 8u * cap ? lz : 8u * cap) >> 3;
+        ci = (K > 0 && i < cnt_s) ? ci : 0u;
+        codes |= ci << (2 * (EPL - 1 - i));
+        csum += ci;
         prev = q[i];
-        lb += (K != 0 && i < cur.cnt[s]) ? (uint32_t)(nb - ci) : 0u;
       }
+      // stored bytes of the lane: nb per valid value less the identical ones
+      const uint32_t lb = K != 0 ? (uint32_t)(nb * cnt_s) - csum : 0u;
       uint32_t rtot;
       const uint32_t ex = wg_excl_sum<uint32_t>(lb, s_scan, rtot);
       if (K != 0) {
@@ -592,14 +588,17 @@ __device__ __forceinline__ void encode_pass(const CBatch& b, uint32_t* s_scan, u
           for (int j = 0; j < EPL / 4; ++j) cdst[j] = (uint8_t)(codes >> (8 * (EPL / 4 - 1 - j)));
         }
       }
-      // stage the kept bytes of each value, most significant first
+      // stage the kept bytes of each value, most significant first: q holds
+      // only its top nb bytes, so after the byte swap the value's string is
+      // img >> 8 ci with zero bytes above it (ci <= 3 keeps the shift < 32)
       LanePacker pk(s_stage, tile_bytes + ex);
 #pragma unroll
       for (int i = 0; i < EPL; ++i) {
         const int ci = (int)((codes >> (2 * (EPL - 1 - i))) & 3u);
-        const int Li = (K != 0 && i < cur.cnt[s]) ? nb - ci : 0;
+        const bool valid = K != 0 && i < cnt_s;
+        const int Li = valid ? nb - ci : 0;
         const U img = raw ? q[i] : byte_swap(q[i]);
-        const U sv = Li > 0 ? (U)((img >> (8 * ci)) & low_bytes_mask<U>(Li)) : (U)0;
+        const U sv = valid ? (U)(img >> (8 * ci)) : (U)0;
         pk.put(sv, Li);
       }
       pk.flush();

@@ -235,6 +235,10 @@ __device__ __forceinline__ int same_lead_bytes(uint64_t a, uint64_t b) {
   return z == 0 ? 8 : (__clzll(z) >> 3);
 }
 
+// Leading zero bits of z; any value >= the width for z = 0 (callers cap it).
+__device__ __forceinline__ uint32_t lead_zero_bits(uint32_t z) { return (uint32_t)__clz((int)z); }
+__device__ __forceinline__ uint32_t lead_zero_bits(uint64_t z) { return (uint32_t)__clzll((long long)z); }
+
 __device__ __forceinline__ uint32_t byte_swap(uint32_t v) { return __builtin_bswap32(v); }
 __device__ __forceinline__ uint64_t byte_swap(uint64_t v) { return __builtin_bswap64(v); }
 
@@ -242,9 +246,46 @@ __device__ __forceinline__ uint64_t byte_swap(uint64_t v) { return __builtin_bsw
 
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
+// Inclusive sum of 32-bit values over the 64 lanes of a wave with DPP: row
+// shifts by 1, 2, 4, 8 within each row of 16 lanes, then the last lane of
+// rows 0 and 2 added to rows 1 and 3 (row_bcast:15) and the last lane of row 1
+// to rows 2 and 3 (row_bcast:31). Lanes without a source add 0. No LDS.
+__device__ __forceinline__ uint32_t wave_incl_sum_u32(uint32_t v) {
+  int x = (int)v;
+  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xF, 0xF, false);  // row_shr:1
+  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xF, 0xF, false);  // row_shr:2
+  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xF, 0xF, false);  // row_shr:4
+  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xF, 0xF, false);  // row_shr:8
+  x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false);  // row_bcast:15
+  x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false);  // row_bcast:31
+  return (uint32_t)x;
+}
+
+// The value of the previous lane within groups of G <= 16 lanes (row_shr:1;
+// the first lane of each row of 16 gets 0, other group starts get their
+// neighbour, which callers replace).
+__device__ __forceinline__ uint32_t lane_before_u32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, false);
+}
+template <int G, typename U>
+__device__ __forceinline__ U lane_before(U v) {
+  if constexpr (G <= 16) {
+    if constexpr (sizeof(U) == 4) {
+      return (U)lane_before_u32((uint32_t)v);
+    } else {
+      const uint32_t lo = lane_before_u32((uint32_t)v);
+      const uint32_t hi = lane_before_u32((uint32_t)(v >> 32));
+      return ((U)hi << 32) | lo;
+    }
+  } else {
+    return __shfl_up(v, 1, G);
+  }
+}
+
 // Inclusive sum over groups of G consecutive lanes (G a power of two <= 64).
 template <int G, typename V>
 __device__ __forceinline__ V group_incl_sum(V v) {
+  if constexpr (G == 64 && sizeof(V) == 4) return (V)wave_incl_sum_u32((uint32_t)v);
   const int lg = lane_id() & (G - 1);
 #pragma unroll
   for (int d = 1; d < G; d <<= 1) {
