@@ -257,6 +257,13 @@ __device__ __forceinline__ BlockPlan<T> plan_block(typename Traits<T>::U kmin, t
   return p;
 }
 
+// A block's plan in one byte: 0 constant, 0xFF raw, else K with bit 7 set
+// when the values must be verified.
+template <typename T>
+__device__ __forceinline__ uint32_t plan_byte(const BlockPlan<T>& p) {
+  return p.K < 0 ? 0xFFu : (uint32_t)p.K | (p.verify ? 0x80u : 0u);
+}
+
 // -------------------------------------------------------------- classify ---
 
 // mu and the constant test of every block, the state bits, and the rank of the
@@ -270,7 +277,7 @@ __device__ __forceinline__ void classify_tile(const FieldC& f, uint32_t t, uint3
   constexpr int TBLK = G::TBLK;
   constexpr int CLS = TBLK > 1024 ? TBLK : 1024;
   constexpr int BPT = CLS / kWG;  // blocks per thread
-  const U* stats = reinterpret_cast<const U*>(f.stats);
+  U* stats = reinterpret_cast<U*>(f.stats);
   const uint64_t nblk = f.nblk;
   const uint64_t k0 = (uint64_t)t * CLS + (uint64_t)threadIdx.x * BPT;
   U kmin[BPT], kmax[BPT];
@@ -294,6 +301,10 @@ __device__ __forceinline__ void classify_tile(const FieldC& f, uint32_t t, uint3
     if (k < nblk) {
       const BlockPlan<T> p = plan_block<T>(kmin[i], kmax[i], e);
       mus[k] = p.mu;
+      // the extrema are not read again: their two words now carry mu and the
+      // block's plan byte for the encode pass
+      stats[2 * k] = bits_of(p.mu);
+      stats[2 * k + 1] = (U)plan_byte(p);
       const bool nc = p.K != 0;
       cnt += nc ? 1u : 0u;
       bits |= (nc ? 1u : 0u) << i;
@@ -441,13 +452,14 @@ struct TileIn {
   uint64_t n_nc;                  // read with the tile so their latency hides too
 };
 
-// Loads and plans tile t: extrema, plan, ranks within the tile (barriers),
-// and the values of its non-constant blocks (left in flight).
+// Loads tile t: each block's mu and plan byte (left by the classification
+// pass in the block's extrema words), ranks within the tile (barriers), and
+// the values of its non-constant blocks (left in flight).
 template <typename T, int B>
 __device__ __forceinline__ void tile_load(TileIn<T, B>& in, uint32_t t, const T* __restrict__ x,
                                           const typename Traits<T>::U* __restrict__ stats,
                                           const uint64_t* __restrict__ enc_r0, uint64_t n, uint64_t nblk,
-                                          T e, uint32_t* s_scan) {
+                                          uint32_t* s_scan) {
   using G = Geo<T, B>;
   constexpr int EPL = G::EPL, LPB = G::LPB, TB = G::TB, SUB = G::SUB, TBLK = G::TBLK;
   const int g = threadIdx.x / LPB, lig = threadIdx.x % LPB;
@@ -456,24 +468,26 @@ __device__ __forceinline__ void tile_load(TileIn<T, B>& in, uint32_t t, const T*
 #pragma unroll
   for (int s = 0; s < SUB; ++s) {
     const uint64_t k = (uint64_t)t * TBLK + (uint64_t)s * TB + g;
-    BlockPlan<T> p;
-    p.mu = (T)0;
-    p.K = 0;
-    p.verify = false;
-    if (k < nblk) p = plan_block<T>(stats[2 * k], stats[2 * k + 1], e);
-    in.mu[s] = p.mu;
-    in.K[s] = p.K;
-    in.verify[s] = p.verify;
-    const uint64_t nk = (k < nblk && p.K != 0) ? std::min<uint64_t>((uint64_t)B, n - k * B) : 0;
+    using U = typename Traits<T>::U;
+    U mub = 0, pb = 0;
+    if (k < nblk) {
+      mub = stats[2 * k];
+      pb = stats[2 * k + 1];
+    }
+    const int K = pb == 0xFFu ? -1 : (int)(pb & 0x7Fu);
+    in.mu[s] = from_bits<T>(mub);
+    in.K[s] = K;
+    in.verify[s] = (pb & 0x80u) != 0 && pb != 0xFFu;
+    const uint64_t nk = (k < nblk && K != 0) ? std::min<uint64_t>((uint64_t)B, n - k * B) : 0;
     in.cnt[s] = (int)((uint64_t)lig * EPL >= nk ? 0 : std::min<uint64_t>(EPL, nk - (uint64_t)lig * EPL));
     load_run<T, EPL>(x, k * B + (uint64_t)lig * EPL, k * B + nk, in.x[s]);
-    first[s] = (lig == 0 && p.K != 0) ? 1u : 0u;
+    first[s] = (lig == 0 && K != 0) ? 1u : 0u;
   }
   uint32_t tot[SUB];
   wg_excl_scan_multi<SUB>(first, in.rank, tot, s_scan);
-  const int lane = lane_id();
+  // the group's first lane counted its block; the others see it counted
 #pragma unroll
-  for (int s = 0; s < SUB; ++s) in.rank[s] = __shfl(in.rank[s], lane - lig);
+  for (int s = 0; s < SUB; ++s) in.rank[s] -= (lig != 0 && in.K[s] != 0) ? 1u : 0u;
 }
 
 // The encode pass for the tiles of element type T: persistent workgroups take
@@ -510,7 +524,7 @@ __device__ __forceinline__ void encode_pass(const CBatch& b, uint32_t* s_scan, u
     in.e = from_bits<T>((U)f.ctr->e_bits);
     in.n_nc = f.ctr->n_nc;
     tile_load<T, B>(in, in.tile, reinterpret_cast<const T*>(f.in), reinterpret_cast<const U*>(f.stats), f.enc_r0,
-                    f.n, f.nblk, in.e, s_scan);
+                    f.n, f.nblk, s_scan);
   };
 
   for (int i = threadIdx.x; i < STAGE_WORDS / 4; i += kWG)
