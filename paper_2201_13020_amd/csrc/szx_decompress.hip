@@ -99,9 +99,23 @@ __device__ __forceinline__ uint64_t lds_get<uint64_t>(const uint32_t* stage, uin
   return lds_get64(stage, off);
 }
 
+// The top c bytes of a word for c in [0, 3], branch-free: the top three
+// bytes shifted left by 8 (3 - c) (c = 0 shifts them out entirely).
 template <typename U>
-__device__ __forceinline__ U low_mask(int L) {
-  return L >= (int)sizeof(U) ? (U)~(U)0 : (U)(((U)1 << (8 * L)) - 1);
+__device__ __forceinline__ U top_bytes3(uint32_t c) {
+  constexpr U TOP3 = (U)0xFFFFFFu << (sizeof(U) * 8 - 24);
+  return (U)(TOP3 << (8u * (3u - c)));
+}
+
+// Previous lane's value within groups of G lanes (lanes with lig < d get
+// garbage, which callers discard): DPP row shifts for G <= 16.
+template <int G, int D>
+__device__ __forceinline__ uint32_t lane_up(uint32_t v) {
+  if constexpr (G <= 16) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x110 + D, 0xF, 0xF, false);  // row_shr:D
+  } else {
+    return __shfl_up(v, D, G);
+  }
 }
 
 template <typename T, int EPL>
@@ -357,7 +371,8 @@ __device__ __forceinline__ void decode_tile(const FieldD& a, uint32_t t, uint32_
   uint32_t nbytes[SUB];
 #pragma unroll
   for (int s = 0; s < SUB; ++s) {
-    const uint64_t r = r0 + __shfl(rk[s], lane - lig);
+    // the group's first lane counted its block; the others see it counted
+    const uint64_t r = r0 + rk[s] - ((lig != 0 && nc[s]) ? 1u : 0u);
     const bool have = nc[s] && r < h.n_nc;
     bad = bad || (nc[s] && r >= h.n_nc);
     int K = have ? (int)in[h.sec.kbytes + r] : 0;
@@ -417,40 +432,64 @@ __device__ __forceinline__ void decode_tile(const FieldD& a, uint32_t t, uint32_
     } else {
       const int nb = bytes_of(K);
       const int sh = shift_of(K);
+      const U keep = top_bytes_mask<U>(nb);
       U q0[EPL];
       uint32_t cmin[EPL];
       U run = 0;
       uint32_t cm = 3;
 #pragma unroll
       for (int i = 0; i < EPL; ++i) {
-        int ci = (int)((cw[s] >> (2 * (EPL - 1 - i))) & 3u);
-        ci = ci > nb ? nb : ci;
+        uint32_t ci = (cw[s] >> (2 * (EPL - 1 - i))) & 3u;
+        ci = ci > (uint32_t)nb ? (uint32_t)nb : ci;
         const bool live = i < cnt[s];
-        const int L = live ? nb - ci : 0;
+        const uint32_t L = live ? (uint32_t)nb - ci : 0u;
+        // the word at o holds this value's L stored bytes, then whatever
+        // follows; after the shift and byte swap those land below the kept
+        // bytes, where `keep` clears them at the end (ci <= 3: shift < 32)
         const U got = lds_get<U>(s_stage, o < STAGE_WORDS * 4 - 12 ? o : 0);
-        const U sv = (U)((got & low_mask<U>(L)) << (8 * ci));
         o += L;
-        const U stored = byte_swap(sv);
+        const U stored = byte_swap((U)(got << (8 * ci)));
         // values past the end of a short block act as the identity
-        const int cc = live ? ci : 3;
-        run = (run & top_bytes_mask<U>(cc)) | stored;
-        cm = (uint32_t)cc < cm ? (uint32_t)cc : cm;
+        const uint32_t cc = live ? ci : 3u;
+        run = (run & top_bytes3<U>(cc)) | stored;
+        cm = cc < cm ? cc : cm;
         q0[i] = run;
         cmin[i] = cm;
       }
-      // carry of the leading bytes from the lanes before this one in the block
+      // carry of the leading bytes from the lanes before this one in the
+      // block; bytes below the kept ones never reach a kept byte (every mask
+      // here keeps at most the top min(3, nb) bytes of a live value)
       uint32_t pk = top24<U>(run) | cm;
-#pragma unroll
-      for (int d = 1; d < LPB; d <<= 1) {
-        const uint32_t o2 = __shfl_up(pk, d, LPB);
-        pk = lig >= d ? lead_compose(o2, pk) : pk;
+      {
+        uint32_t o2 = lane_up<LPB, 1>(pk);
+        pk = lig >= 1 ? lead_compose(o2, pk) : pk;
+        if constexpr (LPB > 2) {
+          o2 = lane_up<LPB, 2>(pk);
+          pk = lig >= 2 ? lead_compose(o2, pk) : pk;
+        }
+        if constexpr (LPB > 4) {
+          o2 = lane_up<LPB, 4>(pk);
+          pk = lig >= 4 ? lead_compose(o2, pk) : pk;
+        }
+        if constexpr (LPB > 8) {
+          o2 = lane_up<LPB, 8>(pk);
+          pk = lig >= 8 ? lead_compose(o2, pk) : pk;
+        }
+        if constexpr (LPB > 16) {
+          o2 = __shfl_up(pk, 16, LPB);
+          pk = lig >= 16 ? lead_compose(o2, pk) : pk;
+        }
+        if constexpr (LPB > 32) {
+          o2 = __shfl_up(pk, 32, LPB);
+          pk = lig >= 32 ? lead_compose(o2, pk) : pk;
+        }
       }
-      uint32_t carry = __shfl_up(pk, 1, LPB) & 0xFFFFFF00u;
+      uint32_t carry = LPB > 1 ? lane_up<LPB, 1>(pk) & 0xFFFFFF00u : 0u;
       carry = lig == 0 ? 0u : carry;
       const U cfull = from_top24<U>(carry);
 #pragma unroll
       for (int i = 0; i < EPL; ++i) {
-        const U qi = q0[i] | (cfull & top_bytes_mask<U>((int)cmin[i]));
+        const U qi = (q0[i] | (cfull & top_bytes3<U>(cmin[i]))) & keep;
         v[i] = mu[s] + from_bits<T>((U)(qi << sh));
       }
     }
