@@ -111,6 +111,33 @@ __device__ __forceinline__ U group_max(U v) {
   return v;
 }
 
+// Inclusive running min (MAX = false) or max over groups of G consecutive
+// lanes: the group's last lane ends with the group's extremum. DPP row shifts
+// for G <= 16 (no LDS), lane shuffles otherwise.
+template <int G, typename U, bool MAX>
+__device__ __forceinline__ U group_scan_last(U v) {
+  if constexpr (G == 1) {
+    return v;
+  } else if constexpr (G <= 16) {
+    const int lg = lane_id() & (G - 1);
+#pragma unroll
+    for (int d = 1; d < G; d <<= 1) {
+      U o;
+      if constexpr (sizeof(U) == 4) {
+        o = (U)dpp_shr(d, (uint32_t)v);
+      } else {
+        const uint32_t lo = dpp_shr(d, (uint32_t)v), hi = dpp_shr(d, (uint32_t)(v >> 32));
+        o = ((U)hi << 32) | lo;
+      }
+      const U m = MAX ? (o > v ? o : v) : (o < v ? o : v);
+      v = lg >= d ? m : v;
+    }
+    return v;
+  } else {
+    return MAX ? group_max<G, U>(v) : group_min<G, U>(v);
+  }
+}
+
 // ----------------------------------------------------------------- stats ---
 
 // Per-block totalOrder extrema (as keys) of all values over a chunk of
@@ -135,10 +162,11 @@ __device__ __forceinline__ void stats_tile(const T (&v)[Geo<T, B>::EPL], int cnt
     flo = (fin && k < flo) ? k : flo;
     fhi = (fin && k > fhi) ? k : fhi;
   }
-  kmin = group_min<LPB, U>(kmin);
-  kmax = group_max<LPB, U>(kmax);
+  // the block's extrema gather in the group's last lane
+  kmin = group_scan_last<LPB, U, false>(kmin);
+  kmax = group_scan_last<LPB, U, true>(kmax);
   const uint64_t blk = i0 / B;
-  if ((threadIdx.x % LPB) == 0 && blk < nblk) {
+  if ((threadIdx.x % LPB) == LPB - 1 && blk < nblk) {
     stats[2 * blk] = kmin;
     stats[2 * blk + 1] = kmax;
   }
@@ -275,7 +303,7 @@ __device__ __forceinline__ void classify_tile(const FieldC& f, uint32_t t, uint3
   using U = typename Traits<T>::U;
   using G = Geo<T, B>;
   constexpr int TBLK = G::TBLK;
-  constexpr int CLS = TBLK > 1024 ? TBLK : 1024;
+  constexpr int CLS = TBLK > (int)kClsMin ? TBLK : (int)kClsMin;
   constexpr int BPT = CLS / kWG;  // blocks per thread
   U* stats = reinterpret_cast<U*>(f.stats);
   const uint64_t nblk = f.nblk;
@@ -333,7 +361,7 @@ __device__ __forceinline__ void classify_tile(const FieldC& f, uint32_t t, uint3
 
 template <typename T, int B>
 __global__ __launch_bounds__(256) void k_classify(CBatch b) {
-  constexpr int CLS = Geo<T, B>::TBLK > 1024 ? Geo<T, B>::TBLK : 1024;
+  constexpr int CLS = Geo<T, B>::TBLK > (int)kClsMin ? Geo<T, B>::TBLK : (int)kClsMin;
   __shared__ uint32_t s_scan[kWavesPerWG];
   __shared__ uint32_t s_state[CLS / 32 > 32 ? CLS / 32 : 32];
   __shared__ uint64_t s_base;

@@ -225,7 +225,7 @@ __device__ __forceinline__ void dindex_tile(const FieldD& a, uint32_t t, uint32_
   using G = Geo<T, B>;
   constexpr int BYTES = Traits<T>::BYTES;
   constexpr int TBLK = G::TBLK;
-  constexpr int CLS = TBLK > 1024 ? TBLK : 1024;
+  constexpr int CLS = TBLK > (int)kClsMin ? TBLK : (int)kClsMin;
   constexpr int BPT = CLS / kWG;
   uint64_t& s_r0 = *s_r0p;
   uint64_t& s_m0 = *s_m0p;

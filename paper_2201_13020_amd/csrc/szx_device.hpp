@@ -261,6 +261,17 @@ __device__ __forceinline__ uint32_t wave_incl_sum_u32(uint32_t v) {
   return (uint32_t)x;
 }
 
+// Lane i - d within each row of 16 lanes (row_shr:d, d in {1, 2, 4, 8});
+// the first d lanes of a row get 0.
+__device__ __forceinline__ uint32_t dpp_shr(int d, uint32_t v) {
+  switch (d) {
+    case 1: return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, false);
+    case 2: return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, false);
+    case 4: return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, false);
+    default: return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, false);
+  }
+}
+
 // The value of the previous lane within groups of G <= 16 lanes (row_shr:1;
 // the first lane of each row of 16 gets 0, other group starts get their
 // neighbour, which callers replace).

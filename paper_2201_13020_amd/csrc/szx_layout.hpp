@@ -59,17 +59,19 @@ __host__ __device__ inline uint32_t tile_blocks(uint32_t b, uint32_t w) {
   return tb * sub;
 }
 
-// Blocks per tile of the classification pass: a multiple of every encode
-// tile, four blocks per thread at most.
+// Blocks per tile of the classification and index passes: at least
+// kClsMin (a multiple of 256, the workgroup size) and a multiple of every
+// encode tile.
+constexpr uint32_t kClsMin = 1024;
 __host__ __device__ inline uint32_t cls_blocks(uint32_t b, uint32_t w) {
   const uint32_t t = tile_blocks(b, w);
-  return t > 1024 ? t : 1024;
+  return t > kClsMin ? t : kClsMin;
 }
 
 // Ticket classes of the persistent encode pass (per element type).
 constexpr uint32_t kTicketClasses = 8;
 // Tiles of the extrema pass per chunk; a chunk leaves one finite range.
-constexpr uint32_t kStatsChunk = 8;
+constexpr uint32_t kStatsChunk = 2;
 
 // The extrema pass folds each chunk's finite range into one of a field's
 // range slots (chunk c into slot c mod slots), by 64-bit atomic maxima of
