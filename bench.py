@@ -71,8 +71,9 @@ def kernel_bytes(name, n, w, nblk, n_nc, mid_total, b=BLOCK):
     """Algorithmic HBM bytes of one launch of each kernel (reads + writes),
     from the sizes of the arrays each kernel must touch once."""
     codes = n_nc * (b // 4)
-    tblk = 64 if w == 4 else 32  # blocks per encode/decode tile at b = 128
+    tblk = 64 if w == 4 else 32  # blocks per encode tile at b = 128 (32 KiB of input)
     ntile = -(-nblk // tblk)
+    ndtile = -(-nblk // (tblk // 2))  # decode tiles: 16 KiB of input
     if name == "k_stats":  # values in; per-block extrema out
         return n * w + nblk * 2 * w
     if name == "k_classify":  # extrema in; mu, state bits, tile ranks out; (mu, plan) over the extrema
@@ -80,9 +81,9 @@ def kernel_bytes(name, n, w, nblk, n_nc, mid_total, b=BLOCK):
     if name == "k_encode":  # (mu, plan) words, tile ranks, non-constant values in; K, codes, mid out
         return nblk * 2 * w + 8 * ntile + n_nc * b * w + n_nc + codes + mid_total
     if name == "k_dindex":  # state bits, K, codes in; tile index out
-        return nblk / 8 + n_nc + codes + 16 * ntile
+        return nblk / 8 + n_nc + codes + 16 * ndtile
     if name == "k_decode":  # index, state, mu, K, codes, mid in; values out
-        return 16 * ntile + nblk / 8 + nblk * w + n_nc + codes + mid_total + n * w
+        return 16 * ndtile + nblk / 8 + nblk * w + n_nc + codes + mid_total + n * w
     return 0
 
 

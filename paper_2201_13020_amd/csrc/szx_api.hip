@@ -339,7 +339,7 @@ sz_status plan_decompress(const sz_dfield* fs, uint32_t n, uint8_t* ws, std::vec
     if (s != SZ_OK) return s;
     const szx::FieldTiles ft = szx::field_tiles(jobs[i].n, jobs[i].nblk, jobs[i].w, block);
     P.tiles[0 + jobs[i].dtype] += ft.cls;
-    P.tiles[2 + jobs[i].dtype] += ft.enc;
+    P.tiles[2 + jobs[i].dtype] += ft.dec;
   }
   uint64_t off = 256;
   P.fields_off = off;
@@ -361,7 +361,7 @@ sz_status plan_decompress(const sz_dfield* fs, uint32_t n, uint8_t* ws, std::vec
   for (uint32_t i = 0; i < n; ++i) {
     const szx::FieldTiles ft = szx::field_tiles(jobs[i].n, jobs[i].nblk, jobs[i].w, block);
     index_off[i] = off;
-    off = a256(off + (ft.enc + 1) * 16);
+    off = a256(off + (ft.dec + 1) * 16);
   }
   P.total = off;
   if (!host) return SZ_OK;
@@ -396,9 +396,9 @@ sz_status plan_decompress(const sz_dfield* fs, uint32_t n, uint8_t* ws, std::vec
     f.base_dec = bd[dt];
     F[i] = f;
     for (uint64_t t = 0; t < ft.cls; ++t) maps[0 + dt][bi[dt] + t] = i;
-    for (uint64_t t = 0; t < ft.enc; ++t) maps[2 + dt][bd[dt] + t] = i;
+    for (uint64_t t = 0; t < ft.dec; ++t) maps[2 + dt][bd[dt] + t] = i;
     bi[dt] += ft.cls;
-    bd[dt] += ft.enc;
+    bd[dt] += ft.dec;
   }
   szx::DBatch& b = *bout;
   memset(&b, 0, sizeof b);
@@ -489,7 +489,7 @@ sz_status sz_decompress(const void* d_in, uint64_t in_bytes, const sz_params* ex
   memset(&b, 0, sizeof b);
   b.one = single_field_d(j, d_in, in_bytes, d_out, d_status, ws);
   b.tiles_idx[j.dtype] = ft.cls;
-  b.tiles_dec[j.dtype] = ft.enc;
+  b.tiles_dec[j.dtype] = ft.dec;
   b.zero_begin = (uint64_t*)(ws + W.dec_rank);
   b.zero_words = (W.zero_end - W.dec_rank) / 8;
   b.nfields = 1;

@@ -222,7 +222,7 @@ __device__ __forceinline__ uint32_t block_mid_bytes(const uint8_t* cp, uint32_t 
 template <typename T, int B>
 __device__ __forceinline__ void dindex_tile(const FieldD& a, uint32_t t, uint32_t* s_scan, uint64_t* s_r0p,
                                             uint64_t* s_m0p) {
-  using G = Geo<T, B>;
+  using G = Geo<T, B>;  // classification tiles follow the encode geometry
   constexpr int BYTES = Traits<T>::BYTES;
   constexpr int TBLK = G::TBLK;
   constexpr int CLS = TBLK > (int)kClsMin ? TBLK : (int)kClsMin;
@@ -279,15 +279,16 @@ __device__ __forceinline__ void dindex_tile(const FieldD& a, uint32_t t, uint32_
   }
   __syncthreads();
   const uint64_t M0 = s_m0;
-  if ((k0 % TBLK) == 0 && k0 < a.nblk) {
-    a.index[2 * (k0 / TBLK)] = R0 + rex;
-    a.index[2 * (k0 / TBLK) + 1] = M0 + mex;
+  constexpr int DTBLK = GeoD<T, B>::TBLK;  // index entries per decode tile
+  if ((k0 % DTBLK) == 0 && k0 < a.nblk) {
+    a.index[2 * (k0 / DTBLK)] = R0 + rex;
+    a.index[2 * (k0 / DTBLK) + 1] = M0 + mex;
   }
   if (t == ntiles - 1 && threadIdx.x == 0) {
     if (R0 + tnc != h.n_nc || M0 + tmid != h.mid_total) bad = true;
     // the end of the last decode tile
-    a.index[2 * cdiv(a.nblk, TBLK)] = h.n_nc;
-    a.index[2 * cdiv(a.nblk, TBLK) + 1] = h.mid_total;
+    a.index[2 * cdiv(a.nblk, DTBLK)] = h.n_nc;
+    a.index[2 * cdiv(a.nblk, DTBLK) + 1] = h.mid_total;
   }
   if (__ballot(bad) != 0 && lane_id() == 0) atomicMax(a.status, kStatusCorrupt);
 }
@@ -304,7 +305,7 @@ __global__ __launch_bounds__(256) void k_dindex(DBatch b) {
 template <typename T, int B>
 __device__ __forceinline__ void decode_tile(const FieldD& a, uint32_t t, uint32_t* s_scan, uint32_t* s_stage) {
   using U = typename Traits<T>::U;
-  using G = Geo<T, B>;
+  using G = GeoD<T, B>;
   constexpr int EPL = G::EPL, LPB = G::LPB, TB = G::TB, SUB = G::SUB, TBLK = G::TBLK;
   constexpr int BYTES = Traits<T>::BYTES;
   constexpr int STAGE_WORDS = (G::TILE * SUB * BYTES + 32) / 4 + 8;
@@ -501,7 +502,7 @@ __device__ __forceinline__ void decode_tile(const FieldD& a, uint32_t t, uint32_
 
 template <typename T, int B>
 __global__ __launch_bounds__(256) void k_decode(DBatch b) {
-  using G = Geo<T, B>;
+  using G = GeoD<T, B>;
   __shared__ uint32_t s_scan[G::SUB * kWavesPerWG];
   __shared__ __align__(16) uint32_t s_stage[(G::TILE * G::SUB * Traits<T>::BYTES + 32) / 4 + 8];
   const uint64_t g = blockIdx.x;

@@ -10,6 +10,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "szx_layout.hpp"
+
 namespace szx {
 
 // A pointer read from a field descriptor in memory is typed generic, so every
@@ -57,27 +59,33 @@ struct Traits<double> {
 // Launch geometry that depends only on the block size b: each lane owns EPL
 // consecutive values, LPB lanes share one block, a 256-thread workgroup tile
 // holds TB whole blocks. It changes no output byte.
-// A tile of the encode/decode passes is SUB such rows of TB blocks (about
-// 32 KiB of input, and at least 8 blocks so that a tile owns whole bytes of
-// the state bits), so that the per-tile costs of the prefix sums are rare.
-constexpr int geo_sub(int tile_bytes, int tb) {
-  int s = 32768 / tile_bytes;
+// A tile is SUB such rows of TB blocks: about TARGET bytes of input (and at
+// least 8 blocks, so that a tile owns whole bytes of the state bits). The
+// encoder's tiles are large, so that the per-tile costs of its prefix sums
+// are rare; the decoder's are half that size, so that more workgroups fit a
+// compute unit (its tiles wait on nothing).
+constexpr int geo_sub(int tile_bytes, int tb, int target) {
+  int s = target / tile_bytes;
   s = s < 1 ? 1 : s;
   while (tb * s < 8) s *= 2;
   return s;
 }
 
-template <typename T, int B>
+template <typename T, int B, int TARGET = (int)kEncodeTileBytes>
 struct Geo {
   static constexpr int EPL = B >= 512 ? B / 64 : 8;
   static constexpr int LPB = B / EPL;  // 1..64, divides 64
   static constexpr int TB = kWG / LPB;
   static constexpr int TILE = TB * B;  // values per row
-  static constexpr int SUB = geo_sub(TILE * (int)sizeof(T), TB);
+  static constexpr int SUB = geo_sub(TILE * (int)sizeof(T), TB, TARGET);
   static constexpr int TBLK = TB * SUB;  // blocks per tile
   static_assert(LPB >= 1 && LPB <= 64 && (64 % LPB) == 0, "group must fit a wave");
   static_assert(TBLK % 8 == 0, "a tile owns whole state bytes");
 };
+
+// Decoder tiles (each a whole number of them per encode tile).
+template <typename T, int B>
+using GeoD = Geo<T, B, (int)kDecodeTileBytes>;
 
 __device__ __forceinline__ uint32_t bits_of(float v) { return __float_as_uint(v); }
 __device__ __forceinline__ uint64_t bits_of(double v) { return (uint64_t)__double_as_longlong(v); }

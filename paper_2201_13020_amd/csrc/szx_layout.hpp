@@ -47,13 +47,19 @@ struct Job {
   uint32_t w;
 };
 
-// Blocks per tile of the encode/decode passes for block size b and element
-// size w (mirrors Geo in szx_device.hpp).
-__host__ __device__ inline uint32_t tile_blocks(uint32_t b, uint32_t w) {
+// Input bytes per tile of the encode and of the decode pass (targets; a tile
+// is a whole number of rows and at least 8 blocks). A decode tile divides an
+// encode tile.
+constexpr uint32_t kEncodeTileBytes = 32768;
+constexpr uint32_t kDecodeTileBytes = 16384;
+
+// Blocks per tile of the encode (or, with kDecodeTileBytes, the decode) pass
+// for block size b and element size w (mirrors Geo in szx_device.hpp).
+__host__ __device__ inline uint32_t tile_blocks(uint32_t b, uint32_t w, uint32_t target = kEncodeTileBytes) {
   const uint32_t epl = b >= 512 ? b / 64 : 8;
   const uint32_t lpb = b / epl;
   const uint32_t tb = 256 / lpb;
-  uint32_t sub = 32768 / (tb * b * w);
+  uint32_t sub = target / (tb * b * w);
   sub = sub < 1 ? 1 : sub;
   while (tb * sub < 8) sub *= 2;
   return tb * sub;
@@ -92,7 +98,8 @@ __host__ __device__ inline uint64_t row_values(uint32_t b) { return 256ull * (b 
 struct FieldTiles {
   uint64_t chunks;  // extrema pass
   uint64_t cls;     // classification / decoder index tiles
-  uint64_t enc;     // encode / decode tiles
+  uint64_t enc;     // encode tiles
+  uint64_t dec;     // decode tiles
 };
 
 __host__ __device__ inline FieldTiles field_tiles(uint64_t n, uint64_t nblk, uint32_t w, uint32_t b) {
@@ -100,6 +107,7 @@ __host__ __device__ inline FieldTiles field_tiles(uint64_t n, uint64_t nblk, uin
   t.chunks = cdiv(cdiv(n, row_values(b)), kStatsChunk);
   t.cls = cdiv(nblk, cls_blocks(b, w));
   t.enc = cdiv(nblk, tile_blocks(b, w));
+  t.dec = cdiv(nblk, tile_blocks(b, w, kDecodeTileBytes));
   return t;
 }
 
@@ -124,7 +132,7 @@ __host__ __device__ inline WsLayout ws_layout(uint64_t n, uint64_t nblk, uint32_
   L.stats = L.zero_end;
   L.enc_r0 = align256(L.stats + nblk * 2 * (uint64_t)w);
   L.dec_index = align256(L.enc_r0 + (ft.enc + 1) * 8);
-  L.total = align256(L.dec_index + (ft.enc + 1) * 16);
+  L.total = align256(L.dec_index + (ft.dec + 1) * 16);
   return L;
 }
 
