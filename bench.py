@@ -76,10 +76,10 @@ def kernel_bytes(name, n, w, nblk, n_nc, mid_total, b=BLOCK):
     ndtile = -(-nblk // (tblk // 2))  # decode tiles: 16 KiB of input
     if name == "k_stats":  # values in; per-block extrema out
         return n * w + nblk * 2 * w
-    if name == "k_classify":  # extrema in; mu, state bits, tile ranks out; (mu, plan) over the extrema
-        return nblk * 2 * w + nblk * w + nblk / 8 + 8 * ntile + nblk * 2 * w
-    if name == "k_encode":  # (mu, plan) words, tile ranks, non-constant values in; K, codes, mid out
-        return nblk * 2 * w + 8 * ntile + n_nc * b * w + n_nc + codes + mid_total
+    if name == "k_classify":  # extrema in; mu, state bits, plan bytes, tile ranks out
+        return nblk * 2 * w + nblk * w + nblk / 8 + nblk + 8 * ntile
+    if name == "k_encode":  # mu, plan bytes, tile ranks, non-constant values in; K, codes, mid out
+        return nblk * w + nblk + 8 * ntile + n_nc * b * w + n_nc + codes + mid_total
     if name == "k_dindex":  # state bits, K, codes in; tile index out
         return nblk / 8 + n_nc + codes + 16 * ndtile
     if name == "k_decode":  # index, state, mu, K, codes, mid in; values out

@@ -135,6 +135,7 @@ szx::FieldC single_field_c(const szx::Job& j, const void* in, void* out, uint64_
   f.range = (uint64_t*)(ws + W.range);
   f.nslots = szx::range_slots(ft.chunks);
   f.stats = ws + W.stats;
+  f.plan = ws + W.plan;
   f.enc_r0 = (uint64_t*)(ws + W.enc_r0);
   f.cls_status = (uint64_t*)(ws + W.cls_status);
   f.enc_mid = (uint64_t*)(ws + W.enc_mid);
@@ -250,11 +251,13 @@ sz_status plan_compress(const sz_cfield* fs, uint32_t n, uint8_t* ws, std::vecto
     off = a256(off + (ft.enc + 1) * 8);
   }
   P.zero_end = off;
-  std::vector<uint64_t> stats_off(n), r0_off(n);
+  std::vector<uint64_t> stats_off(n), plan_off(n), r0_off(n);
   for (uint32_t i = 0; i < n; ++i) {
     const szx::FieldTiles ft = szx::field_tiles(jobs[i].n, jobs[i].nblk, jobs[i].w, block);
     stats_off[i] = off;
     off = a256(off + jobs[i].nblk * 2 * (uint64_t)jobs[i].w);
+    plan_off[i] = off;
+    off = a256(off + jobs[i].nblk);
     r0_off[i] = off;
     off = a256(off + (ft.enc + 1) * 8);
   }
@@ -291,6 +294,7 @@ sz_status plan_compress(const sz_cfield* fs, uint32_t n, uint8_t* ws, std::vecto
     f.range = (uint64_t*)(ws + ctr_off[i] + 256);
     f.nslots = szx::range_slots(ft.chunks);
     f.stats = ws + stats_off[i];
+    f.plan = ws + plan_off[i];
     f.enc_r0 = (uint64_t*)(ws + r0_off[i]);
     f.cls_status = (uint64_t*)(ws + cls_off[i]);
     f.enc_mid = (uint64_t*)(ws + mid_off[i]);

@@ -42,6 +42,7 @@ __device__ __forceinline__ FieldC field_at(const CBatch& b, uint32_t fi) {
   f.ctr = as_global(f.ctr);
   f.range = as_global(f.range);
   f.stats = as_global(f.stats);
+  f.plan = as_global(f.plan);
   f.enc_r0 = as_global(f.enc_r0);
   f.cls_status = as_global(f.cls_status);
   f.enc_mid = as_global(f.enc_mid);
@@ -305,7 +306,7 @@ __device__ __forceinline__ void classify_tile(const FieldC& f, uint32_t t, uint3
   constexpr int TBLK = G::TBLK;
   constexpr int CLS = TBLK > (int)kClsMin ? TBLK : (int)kClsMin;
   constexpr int BPT = CLS / kWG;  // blocks per thread
-  U* stats = reinterpret_cast<U*>(f.stats);
+  const U* stats = reinterpret_cast<const U*>(f.stats);
   const uint64_t nblk = f.nblk;
   const uint64_t k0 = (uint64_t)t * CLS + (uint64_t)threadIdx.x * BPT;
   U kmin[BPT], kmax[BPT];
@@ -329,10 +330,7 @@ __device__ __forceinline__ void classify_tile(const FieldC& f, uint32_t t, uint3
     if (k < nblk) {
       const BlockPlan<T> p = plan_block<T>(kmin[i], kmax[i], e);
       mus[k] = p.mu;
-      // the extrema are not read again: their two words now carry mu and the
-      // block's plan byte for the encode pass
-      stats[2 * k] = bits_of(p.mu);
-      stats[2 * k + 1] = (U)plan_byte(p);
+      f.plan[k] = (uint8_t)plan_byte(p);
       const bool nc = p.K != 0;
       cnt += nc ? 1u : 0u;
       bits |= (nc ? 1u : 0u) << i;
@@ -480,12 +478,12 @@ struct TileIn {
   uint64_t n_nc;                  // read with the tile so their latency hides too
 };
 
-// Loads tile t: each block's mu and plan byte (left by the classification
-// pass in the block's extrema words), ranks within the tile (barriers), and
-// the values of its non-constant blocks (left in flight).
+// Loads tile t: each block's mu (from the stream) and plan byte (both left
+// by the classification pass), ranks within the tile (barriers), and the
+// values of its non-constant blocks (left in flight).
 template <typename T, int B>
 __device__ __forceinline__ void tile_load(TileIn<T, B>& in, uint32_t t, const T* __restrict__ x,
-                                          const typename Traits<T>::U* __restrict__ stats,
+                                          const T* __restrict__ mus, const uint8_t* __restrict__ plan,
                                           const uint64_t* __restrict__ enc_r0, uint64_t n, uint64_t nblk,
                                           uint32_t* s_scan) {
   using G = Geo<T, B>;
@@ -496,14 +494,14 @@ __device__ __forceinline__ void tile_load(TileIn<T, B>& in, uint32_t t, const T*
 #pragma unroll
   for (int s = 0; s < SUB; ++s) {
     const uint64_t k = (uint64_t)t * TBLK + (uint64_t)s * TB + g;
-    using U = typename Traits<T>::U;
-    U mub = 0, pb = 0;
+    T mu = (T)0;
+    uint32_t pb = 0;
     if (k < nblk) {
-      mub = stats[2 * k];
-      pb = stats[2 * k + 1];
+      mu = mus[k];
+      pb = plan[k];
     }
     const int K = pb == 0xFFu ? -1 : (int)(pb & 0x7Fu);
-    in.mu[s] = from_bits<T>(mub);
+    in.mu[s] = mu;
     in.K[s] = K;
     in.verify[s] = (pb & 0x80u) != 0 && pb != 0xFFu;
     const uint64_t nk = (k < nblk && K != 0) ? std::min<uint64_t>((uint64_t)B, n - k * B) : 0;
@@ -551,8 +549,8 @@ __device__ __forceinline__ void encode_pass(const CBatch& b, uint32_t* s_scan, u
     in.tile = (uint32_t)(gt - f.base_enc);
     in.e = from_bits<T>((U)f.ctr->e_bits);
     in.n_nc = f.ctr->n_nc;
-    tile_load<T, B>(in, in.tile, reinterpret_cast<const T*>(f.in), reinterpret_cast<const U*>(f.stats), f.enc_r0,
-                    f.n, f.nblk, s_scan);
+    tile_load<T, B>(in, in.tile, reinterpret_cast<const T*>(f.in), reinterpret_cast<const T*>(f.out + f.mu_off),
+                    f.plan, f.enc_r0, f.n, f.nblk, s_scan);
   };
 
   for (int i = threadIdx.x; i < STAGE_WORDS / 4; i += kWG)

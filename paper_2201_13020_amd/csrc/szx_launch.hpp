@@ -24,6 +24,7 @@ struct FieldC {
   Counters* ctr;
   uint64_t* range;      // range slots: slot i at range + i * kRangeStride / 8 (lo_inv, hi)
   void* stats;          // two totalOrder keys per block
+  uint8_t* plan;        // one plan byte per block (classification -> encode)
   uint64_t* enc_r0;     // first rank of every encode tile
   uint64_t* cls_status; // scan status words, classification tiles
   uint64_t* enc_mid;    // scan status words, encode tiles

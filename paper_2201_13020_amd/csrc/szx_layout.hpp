@@ -115,7 +115,7 @@ __host__ __device__ inline FieldTiles field_tiles(uint64_t n, uint64_t nblk, uin
 // status words), then the rest; every piece 256-byte aligned.
 struct WsLayout {
   uint64_t counters, range, tickets, cls_status, enc_mid, dec_rank, dec_mid, zero_end;
-  uint64_t stats, enc_r0, dec_index, total;
+  uint64_t stats, plan, enc_r0, dec_index, total;
 };
 
 __host__ __device__ inline WsLayout ws_layout(uint64_t n, uint64_t nblk, uint32_t w, uint32_t b) {
@@ -130,7 +130,8 @@ __host__ __device__ inline WsLayout ws_layout(uint64_t n, uint64_t nblk, uint32_
   L.dec_mid = align256(L.dec_rank + (ft.cls + 1) * 8);
   L.zero_end = align256(L.dec_mid + (ft.cls + 1) * 8);
   L.stats = L.zero_end;
-  L.enc_r0 = align256(L.stats + nblk * 2 * (uint64_t)w);
+  L.plan = align256(L.stats + nblk * 2 * (uint64_t)w);
+  L.enc_r0 = align256(L.plan + nblk);
   L.dec_index = align256(L.enc_r0 + (ft.enc + 1) * 8);
   L.total = align256(L.dec_index + (ft.dec + 1) * 16);
   return L;
