@@ -75,9 +75,8 @@ typedef struct {
    priority, and pinned staging). Errors: SZ_EINVAL, SZ_ENOMEM, SZ_EDEVICE. */
 sz_status sz_server_create(const sz_server_config* cfg, sz_server* out);
 
-/* Stop admitting, drop queued requests (they complete with SZ_EINVAL only if
-   polled before this returns; otherwise they are discarded), wait for work in
-   flight, free everything. */
+/* Stop admitting, discard queued requests (no completion is reported for
+   them), wait for work in flight, free everything. */
 void sz_server_destroy(sz_server s);
 
 /* Nanoseconds since the server's creation. */
@@ -111,6 +110,30 @@ sz_status sz_server_copy_item(sz_server s, uint64_t item, void* d_dst, uint64_t 
 sz_status sz_server_release(sz_server s, uint64_t item);
 
 sz_status sz_server_get_stats(sz_server s, sz_server_stats* out);
+
+/* One request of a load trace for sz_server_replay. */
+typedef struct {
+  uint64_t t_arrival;  /* ns on the server clock */
+  uint32_t kind;       /* sz_req_kind */
+  uint32_t pick;       /* decompress: the resident item pool[pick % pool size] */
+  sz_params params;    /* compress */
+  const void* d_in;    /* compress: device input (16-byte aligned) */
+} sz_trace_req;
+
+/* Load driver for measurements: submits the requests in order at their
+   arrival times from the calling thread (spinning on the server clock) and
+   collects completions in between, so that the submitter is not the
+   bottleneck. Completed compressions join a pool of resident items (warm[0..
+   nwarm) first; at most keep items, the oldest released beyond that) from
+   which decompressions pick; decompressions write into the arena and their
+   values are released on completion. A decompression finding the pool empty
+   is skipped (status SZ_EINVAL in its completion). Returns when every
+   request has completed or timeout_ms has passed (SZ_EDEVICE). out[i] is
+   request i's completion; *npool receives the pool's final size and pool its
+   items (capacity max(nwarm, keep)). */
+sz_status sz_server_replay(sz_server s, const sz_trace_req* reqs, uint32_t n, const uint64_t* warm,
+                           uint32_t nwarm, uint32_t keep, uint32_t timeout_ms, sz_completion* out,
+                           uint64_t* pool, uint32_t* npool);
 
 #ifdef __cplusplus
 }

@@ -604,4 +604,75 @@ sz_status sz_server_get_stats(sz_server S, sz_server_stats* out) {
   return SZ_OK;
 }
 
+sz_status sz_server_replay(sz_server S, const sz_trace_req* reqs, uint32_t n, const uint64_t* warm,
+                           uint32_t nwarm, uint32_t keep, uint32_t timeout_ms, sz_completion* out,
+                           uint64_t* pool_out, uint32_t* npool) {
+  clear_error();
+  if (!S || (!reqs && n) || (!out && n) || (!warm && nwarm) || keep == 0)
+    return fail(SZ_EINVAL, "bad replay arguments");
+  std::deque<uint64_t> pool(warm, warm + nwarm);
+  std::unordered_map<uint64_t, uint32_t> index;  // request id -> trace position
+  std::vector<sz_completion> buf(256);
+  uint32_t done = 0;
+  auto collect = [&](uint32_t wait_us) {
+    const uint32_t k = sz_server_poll(S, buf.data(), (uint32_t)buf.size(), wait_us);
+    for (uint32_t i = 0; i < k; ++i) {
+      const sz_completion& c = buf[i];
+      auto it = index.find(c.request);
+      if (it == index.end()) continue;
+      out[it->second] = c;
+      index.erase(it);
+      ++done;
+      if (c.status != SZ_OK) continue;
+      if (c.kind == SZ_REQ_COMPRESS) {
+        pool.push_back(c.item);
+        if (pool.size() > keep) {
+          sz_server_release(S, pool.front());
+          pool.pop_front();
+        }
+      } else if (c.out_item) {
+        sz_server_release(S, c.out_item);
+      }
+    }
+  };
+  for (uint32_t i = 0; i < n; ++i) {
+    const sz_trace_req& r = reqs[i];
+    // wait for the arrival time, collecting completions every 2 us meanwhile
+    uint64_t last = 0;
+    for (uint64_t now = sz_server_clock(S); now < r.t_arrival; now = sz_server_clock(S)) {
+      if (now - last >= 2000) {
+        collect(0);
+        last = now;
+      }
+    }
+    uint64_t id = 0;
+    sz_status st;
+    if (r.kind == SZ_REQ_COMPRESS) {
+      st = sz_server_submit_compress(S, &r.params, r.d_in, r.t_arrival, &id);
+    } else if (pool.empty()) {
+      st = SZ_EINVAL;
+    } else {
+      st = sz_server_submit_decompress(S, pool[r.pick % pool.size()], nullptr, 0, r.t_arrival, &id);
+    }
+    if (st != SZ_OK) {
+      memset(&out[i], 0, sizeof out[i]);
+      out[i].kind = r.kind;
+      out[i].status = st;
+      out[i].t_arrival = r.t_arrival;
+      ++done;
+      continue;
+    }
+    index[id] = i;
+  }
+  const uint64_t t_end = sz_server_clock(S) + (uint64_t)timeout_ms * 1000000ull;
+  while (done < n && sz_server_clock(S) < t_end) collect(1000);
+  if (npool) {
+    *npool = (uint32_t)pool.size();
+    if (pool_out)
+      for (uint32_t i = 0; i < pool.size(); ++i) pool_out[i] = pool[i];
+  }
+  if (done < n) return fail(SZ_EDEVICE, "replay timed out");
+  return SZ_OK;
+}
+
 }  // extern "C"

@@ -28,6 +28,11 @@ class SzCompletion(ctypes.Structure):
                 ("t_done", ctypes.c_uint64), ("group_size", ctypes.c_uint32), ("slot", ctypes.c_uint32)]
 
 
+class SzTraceReq(ctypes.Structure):
+    _fields_ = [("t_arrival", ctypes.c_uint64), ("kind", ctypes.c_uint32), ("pick", ctypes.c_uint32),
+                ("params", szx.SzParams), ("d_in", ctypes.c_void_p)]
+
+
 class SzServerStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in ("arena_bytes", "arena_in_use", "arena_peak", "queued",
                                                "in_flight_groups", "groups_launched", "completed",
@@ -63,6 +68,9 @@ def _lib():
         L.sz_server_release.restype = ctypes.c_int
         L.sz_server_get_stats.argtypes = [vp, ctypes.POINTER(SzServerStats)]
         L.sz_server_get_stats.restype = ctypes.c_int
+        L.sz_server_replay.argtypes = [vp, ctypes.POINTER(SzTraceReq), u32, ctypes.POINTER(u64), u32, u32, u32,
+                                       ctypes.POINTER(SzCompletion), ctypes.POINTER(u64), ctypes.POINTER(u32)]
+        L.sz_server_replay.restype = ctypes.c_int
         _bound = True
     return L
 
@@ -162,75 +170,48 @@ class Server:
         return {f: int(getattr(s, f)) for f, _ in SzServerStats._fields_}
 
 
-def replay(server, trace, bases, eb=1e-3, warm_items=(), keep_items=512, rng_seed=0, timeout_s=600.0):
-    """Submit the requests of `trace` (see synth.serve_trace) at their arrival
-    times and wait for all completions.
-
-    bases: {False: float32 device field, True: float64 device field}; a
-    compression reads a 16-byte-aligned slice of the base of its type.
-    Decompressions write into the arena and their outputs are released as
-    they complete. warm_items: resident items to start the pick pool with;
-    the pool keeps at most keep_items items (the oldest are released).
-    Returns (completions in request order, pool items still resident)."""
-    L = _lib()
+def replay(server, trace, bases, eb=1e-3, warm_items=(), keep_items=512, timeout_s=600.0):
+    """Replay `trace` (see synth.serve_trace) through the server with the
+    library's native load driver (sz_server_replay): requests are submitted
+    at their arrival times, compressions read 16-byte-aligned slices of
+    bases[f64] (a float32 and a float64 device field), decompressions pick
+    resident items and write into the arena (released on completion).
+    warm_items start the pick pool (at most keep_items kept). Returns
+    (completions in request order, pool items still resident)."""
     n = len(trace["t"])
-    t = trace["t"]
-    pool = list(warm_items)
-    pending = {}
-    done = []
-    # parameters built before the clock starts
-    plan = []
+    reqs = (SzTraceReq * max(n, 1))()
+    start = server.clock() + 2_000_000  # 2 ms from now, after this set-up
     for i in range(n):
-        if trace["kind"][i] == SZ_REQ_COMPRESS:
+        r = reqs[i]
+        r.t_arrival = start + int(trace["t"][i] * 1e9)
+        r.kind = int(trace["kind"][i])
+        if r.kind == SZ_REQ_COMPRESS:
             f64 = bool(trace["f64"][i])
             base = bases[f64]
             w = 8 if f64 else 4
             cnt = max(1, int(trace["nbytes"][i]) // w)
             room = base.numel() - cnt
             off = int(trace["pos"][i] * max(room, 0)) // 4 * 4
-            p = szx.make_params(base.dtype, (cnt,), eb, "rel", server.block)
-            plan.append((base, off * w, p))
+            r.params = szx.make_params(base.dtype, (cnt,), eb, "rel", server.block)
+            r.d_in = base.data_ptr() + off * w
         else:
-            plan.append(None)
-
-    def collect(wait_us=0):
-        for c in server.poll(wait_us):
-            kind = pending.pop(c["request"])
-            done.append(c)
-            if c["status"] != 0:
-                continue
-            if kind == SZ_REQ_COMPRESS:
-                pool.append(c["item"])
-                if len(pool) > keep_items:
-                    server.release(pool.pop(0))
-            elif c["out_item"]:
-                server.release(c["out_item"])
-
-    start = server.clock() + 2_000_000  # 2 ms from now
-    rid = ctypes.c_uint64()
-    for i in range(n):
-        due = start + int(t[i] * 1e9)
-        while server.clock() < due:
-            collect()
-        if plan[i] is not None:
-            base, boff, p = plan[i]
-            rc = L.sz_server_submit_compress(server._h, ctypes.byref(p), base.data_ptr() + boff, due, ctypes.byref(rid))
-            _check(rc, "submit compress")
-            pending[rid.value] = SZ_REQ_COMPRESS
-        else:
-            if not pool:
-                continue
-            item = pool[int(trace["pos"][i] * len(pool)) % len(pool)]
-            rc = L.sz_server_submit_decompress(server._h, item, None, 0, due, ctypes.byref(rid))
-            _check(rc, "submit decompress")
-            pending[rid.value] = SZ_REQ_DECOMPRESS
-    t_end = time.time() + timeout_s
-    while pending and time.time() < t_end:
-        collect(10_000)
-    if pending:
-        raise TimeoutError(f"{len(pending)} requests still pending")
-    done.sort(key=lambda c: c["request"])
-    return done, pool
+            r.pick = int(trace["pos"][i] * (1 << 31))
+    if start < server.clock():
+        # set-up took longer than the margin: shift the whole trace
+        lag = server.clock() - start + 1_000_000
+        for i in range(n):
+            reqs[i].t_arrival += lag
+    warm = list(warm_items)
+    cap = max(len(warm), keep_items)
+    warm_arr = (ctypes.c_uint64 * max(len(warm), 1))(*warm)
+    out = (SzCompletion * max(n, 1))()
+    pool = (ctypes.c_uint64 * cap)()
+    npool = ctypes.c_uint32()
+    rc = _lib().sz_server_replay(server._h, reqs, n, warm_arr, len(warm), keep_items, int(timeout_s * 1000), out,
+                                 pool, ctypes.byref(npool))
+    _check(rc, "sz_server_replay")
+    done = [{f: getattr(out[i], f) for f, _ in SzCompletion._fields_} for i in range(n)]
+    return done, [int(pool[i]) for i in range(npool.value)]
 
 
 def summarize(done):
