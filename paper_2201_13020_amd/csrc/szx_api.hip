@@ -89,9 +89,10 @@ std::vector<std::pair<hipStream_t, hipEvent_t>> g_pending;  // begin events by s
 
 void timer_hook(const char* name, hipStream_t s, int begin) {
   std::lock_guard<std::mutex> lock(g_tmu);
+  // measurement only: a failed event call leaves that launch untimed
   hipEvent_t e;
-  hipEventCreate(&e);
-  hipEventRecord(e, s);
+  if (hipEventCreate(&e) != hipSuccess) return;
+  (void)hipEventRecord(e, s);
   if (begin) {
     g_pending.push_back({s, e});
     return;
@@ -102,7 +103,7 @@ void timer_hook(const char* name, hipStream_t s, int begin) {
     g_pending.erase(g_pending.begin() + i);
     return;
   }
-  hipEventDestroy(e);
+  (void)hipEventDestroy(e);
 }
 
 TimerHook current_hook() {
@@ -626,9 +627,9 @@ uint32_t sz_timing_read(const char** names, double* total_ms, uint32_t* launches
   std::vector<double> ms;
   std::vector<uint32_t> cnt;
   for (auto& t : open) {
-    hipEventSynchronize(t.b);
+    (void)hipEventSynchronize(t.b);
     float f = 0.f;
-    hipEventElapsedTime(&f, t.a, t.b);
+    (void)hipEventElapsedTime(&f, t.a, t.b);
     size_t i = 0;
     while (i < nm.size() && strcmp(nm[i], t.name) != 0) ++i;
     if (i == nm.size()) {
@@ -638,8 +639,8 @@ uint32_t sz_timing_read(const char** names, double* total_ms, uint32_t* launches
     }
     ms[i] += f;
     cnt[i] += 1;
-    hipEventDestroy(t.a);
-    hipEventDestroy(t.b);
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
   }
   uint32_t m = (uint32_t)std::min<size_t>(cap, nm.size());
   for (uint32_t i = 0; i < m; ++i) {

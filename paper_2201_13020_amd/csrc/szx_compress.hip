@@ -386,8 +386,9 @@ __device__ __forceinline__ bool encode_try(const T (&x)[EPL], int cnt, T mu, T e
 #pragma unroll
     for (int i = 0; i < EPL; ++i) {
       const T xr = mu + from_bits<T>((U)(q[i] << s));
-      const bool good = exact_le<T>(x[i], xr, e) & exact_le<T>(xr, x[i], e);
-      ok = ok & (good | (i >= cnt));
+      // bitwise on purpose: both checks, no short-circuit branch
+      const bool good = (bool)((int)exact_le<T>(x[i], xr, e) & (int)exact_le<T>(xr, x[i], e));
+      ok = (bool)((int)ok & ((int)good | (int)(i >= cnt)));
       // one value at a time: interleaving all of them costs registers, and
       // this path is rare
       __builtin_amdgcn_sched_barrier(0);
@@ -669,7 +670,8 @@ __device__ __forceinline__ void encode_pass(const CBatch& b, uint32_t* s_scan, u
 }
 
 template <typename T, int B, int BATCH>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_encode(CBatch b) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Geo<T, B>::ENC_WAVES))) void k_encode(
+    CBatch b) {
   using G = Geo<T, B>;
   __shared__ uint32_t s_scan[G::SUB * kWavesPerWG];
   __shared__ uint32_t s_tile;

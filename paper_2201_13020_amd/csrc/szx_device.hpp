@@ -79,6 +79,10 @@ struct Geo {
   static constexpr int TILE = TB * B;  // values per row
   static constexpr int SUB = geo_sub(TILE * (int)sizeof(T), TB, TARGET);
   static constexpr int TBLK = TB * SUB;  // blocks per tile
+  // waves per SIMD the encoder is held to (its LDS stage holds a tile's
+  // output: 4 workgroups of a 32 KiB stage fit the 160 KiB of LDS, one of a
+  // 64 KiB stage leaves room for 2)
+  static constexpr int ENC_WAVES = TILE * SUB * (int)sizeof(T) > 40000 ? 2 : 4;
   static_assert(LPB >= 1 && LPB <= 64 && (64 % LPB) == 0, "group must fit a wave");
   static_assert(TBLK % 8 == 0, "a tile owns whole state bytes");
 };
@@ -233,15 +237,6 @@ __device__ __forceinline__ U top_bytes_mask(int nb) {
   return nb >= W / 8 ? (U)~(U)0 : (nb <= 0 ? (U)0 : (U) ~(((U)1 << (W - 8 * nb)) - 1));
 }
 
-// Count of identical leading bytes of a and b (all bytes when equal).
-__device__ __forceinline__ int same_lead_bytes(uint32_t a, uint32_t b) {
-  const uint32_t z = a ^ b;
-  return z == 0 ? 4 : (__clz(z) >> 3);
-}
-__device__ __forceinline__ int same_lead_bytes(uint64_t a, uint64_t b) {
-  const uint64_t z = a ^ b;
-  return z == 0 ? 8 : (__clzll(z) >> 3);
-}
 
 // Leading zero bits of z; any value >= the width for z = 0 (callers cap it).
 __device__ __forceinline__ uint32_t lead_zero_bits(uint32_t z) { return (uint32_t)__clz((int)z); }

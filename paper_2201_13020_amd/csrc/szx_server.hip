@@ -211,7 +211,7 @@ bool grow_stage(Slot& sl, uint64_t need) {
   if (sl.stage_cap >= need) return true;
   uint64_t cap = sl.stage_cap ? sl.stage_cap : (1 << 20);
   while (cap < need) cap *= 2;
-  if (sl.stage) hipHostFree(sl.stage);
+  if (sl.stage) (void)hipHostFree(sl.stage);  // idle slot: no copy reads it
   sl.stage = nullptr;
   sl.stage_cap = 0;
   if (hipHostMalloc((void**)&sl.stage, cap, hipHostMallocDefault) != hipSuccess) return false;
@@ -272,7 +272,7 @@ void launch_group(sz_server_s* S, uint32_t k, std::unique_ptr<Group> g, const Gr
   if (e == hipSuccess) e = hipEventRecord(sl.done, sl.stream);
   if (e != hipSuccess) {
     // nothing usable was enqueued past the failure; wait for what was
-    hipStreamSynchronize(sl.stream);
+    (void)hipStreamSynchronize(sl.stream);
     fail_group(S, *g, SZ_EDEVICE);
     return;
   }
@@ -333,7 +333,7 @@ void enqueue(sz_server_s* S, Request& r) {
 }
 
 void scheduler_main(sz_server_s* S) {
-  hipSetDevice(S->cfg.device);
+  (void)hipSetDevice(S->cfg.device);  // checked at creation; later calls report any failure
   std::unique_lock<std::mutex> lk(S->mu);
   while (!S->stop) {
     dispatch(S);
@@ -342,7 +342,7 @@ void scheduler_main(sz_server_s* S) {
 }
 
 void completion_main(sz_server_s* S, uint32_t k) {
-  hipSetDevice(S->cfg.device);
+  (void)hipSetDevice(S->cfg.device);  // as in the scheduler
   Slot& sl = *S->slots[k];
   std::unique_lock<std::mutex> lk(S->mu);
   for (;;) {
@@ -473,14 +473,15 @@ void sz_server_destroy(sz_server S) {
   }
   for (auto& sl : S->slots)
     if (sl->th.joinable()) sl->th.join();
-  hipSetDevice(S->cfg.device);
+  // teardown: nothing is left to report a failure to
+  (void)hipSetDevice(S->cfg.device);
   for (auto& sl : S->slots) {
-    if (sl->stream) hipStreamDestroy(sl->stream);
-    if (sl->done) hipEventDestroy(sl->done);
-    if (sl->stage) hipHostFree(sl->stage);
-    if (sl->results) hipHostFree(sl->results);
+    if (sl->stream) (void)hipStreamDestroy(sl->stream);
+    if (sl->done) (void)hipEventDestroy(sl->done);
+    if (sl->stage) (void)hipHostFree(sl->stage);
+    if (sl->results) (void)hipHostFree(sl->results);
   }
-  if (S->base) hipFree(S->base);
+  if (S->base) (void)hipFree(S->base);
   delete S;
 }
 
