@@ -152,24 +152,49 @@ __device__ __forceinline__ void stats_tile(const T (&v)[Geo<T, B>::EPL], int cnt
   using U = typename Traits<T>::U;
   constexpr int EPL = Geo<T, B>::EPL, LPB = Geo<T, B>::LPB;
   U kmin = (U)~(U)0, kmax = 0;
+  if (cnt == EPL) {  // every lane but the field's last partial one
 #pragma unroll
-  for (int i = 0; i < EPL; ++i) {
-    const U u = bits_of(v[i]);
-    const U k = order_key<U>(u);
-    const bool ok = i < cnt;
-    kmin = (ok && k < kmin) ? k : kmin;
-    kmax = (ok && k > kmax) ? k : kmax;
-    const bool fin = ok && is_finite_bits<T>(u);
-    flo = (fin && k < flo) ? k : flo;
-    fhi = (fin && k > fhi) ? k : fhi;
+    for (int i = 0; i < EPL; ++i) {
+      const U k = order_key<U>(bits_of(v[i]));
+      kmin = k < kmin ? k : kmin;
+      kmax = k > kmax ? k : kmax;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < EPL; ++i) {
+      const U k = order_key<U>(bits_of(v[i]));
+      kmin = (i < cnt && k < kmin) ? k : kmin;
+      kmax = (i < cnt && k > kmax) ? k : kmax;
+    }
   }
   // the block's extrema gather in the group's last lane
   kmin = group_scan_last<LPB, U, false>(kmin);
   kmax = group_scan_last<LPB, U, true>(kmax);
   const uint64_t blk = i0 / B;
-  if ((threadIdx.x % LPB) == LPB - 1 && blk < nblk) {
+  const bool last = (threadIdx.x % LPB) == LPB - 1;
+  if (last && blk < nblk) {
     stats[2 * blk] = kmin;
     stats[2 * blk + 1] = kmax;
+  }
+  // finite range: a block whose extrema are finite is finite throughout and
+  // adds [kmin, kmax]; a block holding a NaN or an infinity (rare) adds its
+  // finite values one by one, in every lane of its group
+  const bool finite = kmin >= FiniteKeys<T>::LO && kmax <= FiniteKeys<T>::HI;
+  if (last && finite && blk < nblk) {
+    flo = kmin < flo ? kmin : flo;
+    fhi = kmax > fhi ? kmax : fhi;
+  }
+  const uint64_t odd = __ballot(last && !finite && blk < nblk);
+  const int gl = (lane_id() & ~(LPB - 1)) + LPB - 1;  // the group's last lane
+  if ((odd >> gl) & 1ull) {
+#pragma unroll
+    for (int i = 0; i < EPL; ++i) {
+      const U u = bits_of(v[i]);
+      const U k = order_key<U>(u);
+      const bool fin = i < cnt && is_finite_bits<T>(u);
+      flo = (fin && k < flo) ? k : flo;
+      fhi = (fin && k > fhi) ? k : fhi;
+    }
   }
 }
 
