@@ -603,39 +603,52 @@ __device__ __forceinline__ void encode_pass(const CBatch& b, uint32_t* s_scan, u
     for (int s = 0; s < SUB; ++s) {
       U q[EPL];
       int K = cur.K[s];
-      const bool coded = K > 0;
-      bool ok = encode_try<T, EPL>(cur.x[s], coded ? cur.cnt[s] : 0, cur.mu[s], e, coded ? K : Traits<T>::W,
-                                   coded && cur.verify[s], q);
-      if (!group_all<LPB>(ok)) {  // only coded blocks can fail
-        const int K1 = kept_bits<T>(K - Traits<T>::KMIN + 1);
-        bool ok1 = false;
-        if (K1 != K) ok1 = encode_try<T, EPL>(cur.x[s], cur.cnt[s], cur.mu[s], e, K1, true, q);
-        K = group_all<LPB>(ok1) ? K1 : -1;
-      }
-      const bool raw = K < 0;
-      if (raw) {
-#pragma unroll
-        for (int i = 0; i < EPL; ++i) q[i] = bits_of(cur.x[s][i]);
-      }
-      const int nb = raw ? BYTES : (K > 0 ? bytes_of(K) : 0);
-      U prev = lane_before<LPB, U>(q[EPL - 1]);
-      prev = lig == 0 ? (U)0 : prev;
+      // a wave whose blocks of this row are all constant (or past the end)
+      // stores nothing: it skips to the row's offset scan, which every wave
+      // joins (the vote is wave-uniform, so the branch is too). Only the
+      // 64-bit words pay enough per row for the skip to win; for float32 it
+      // measured no faster and the branch is left out.
+      const bool live = sizeof(T) == 4 || __ballot(K != 0) != 0;
       const int cnt_s = cur.cnt[s];
-      const uint32_t cap = (uint32_t)(nb < 3 ? nb : 3);
-      uint32_t codes = 0, csum = 0;
+      bool raw = false;
+      int nb = 0;
+      uint32_t codes = 0, lb = 0;
+      const bool coded = K > 0;
+      if (live) {
+        bool ok = encode_try<T, EPL>(cur.x[s], coded ? cur.cnt[s] : 0, cur.mu[s], e, coded ? K : Traits<T>::W,
+                                     coded && cur.verify[s], q);
+        if (!group_all<LPB>(ok)) {  // only coded blocks can fail
+          const int K1 = kept_bits<T>(K - Traits<T>::KMIN + 1);
+          bool ok1 = false;
+          if (K1 != K) ok1 = encode_try<T, EPL>(cur.x[s], cur.cnt[s], cur.mu[s], e, K1, true, q);
+          K = group_all<LPB>(ok1) ? K1 : -1;
+        }
+        raw = K < 0;
+        if (raw) {
 #pragma unroll
-      for (int i = 0; i < EPL; ++i) {
-        // leading identical bytes capped at min(3, nb); a zero difference
-        // counts all bytes, which the cap turns into min(3, nb) as well
-        const uint32_t lz = lead_zero_bits(q[i] ^ prev);
-        uint32_t ci = (lz < 8u * cap ? lz : 8u * cap) >> 3;
-        ci = (K > 0 && i < cnt_s) ? ci : 0u;
-        codes |= ci << (2 * (EPL - 1 - i));
-        csum += ci;
-        prev = q[i];
+          for (int i = 0; i < EPL; ++i) q[i] = bits_of(cur.x[s][i]);
+        }
+        nb = raw ? BYTES : (K > 0 ? bytes_of(K) : 0);
+        U prev = lane_before<LPB, U>(q[EPL - 1]);
+        prev = lig == 0 ? (U)0 : prev;
+        const uint32_t cap = (uint32_t)(nb < 3 ? nb : 3);
+        uint32_t csum = 0;
+#pragma unroll
+        for (int i = 0; i < EPL; ++i) {
+          // leading identical bytes capped at min(3, nb); a zero difference
+          // counts all bytes, which the cap turns into min(3, nb) as well. The
+          // cap is at most 24 bits, so a 64-bit word's high half decides it.
+          const U z = q[i] ^ prev;
+          const uint32_t lz = sizeof(U) == 8 ? lead_zero_bits((uint32_t)((uint64_t)z >> 32)) : lead_zero_bits(z);
+          uint32_t ci = (lz < 8u * cap ? lz : 8u * cap) >> 3;
+          ci = (K > 0 && i < cnt_s) ? ci : 0u;
+          codes |= ci << (2 * (EPL - 1 - i));
+          csum += ci;
+          prev = q[i];
+        }
+        // stored bytes of the lane: nb per valid value less the identical ones
+        lb = K != 0 ? (uint32_t)(nb * cnt_s) - csum : 0u;
       }
-      // stored bytes of the lane: nb per valid value less the identical ones
-      const uint32_t lb = K != 0 ? (uint32_t)(nb * cnt_s) - csum : 0u;
       uint32_t rtot;
       const uint32_t ex = wg_excl_sum<uint32_t>(lb, s_scan, rtot);
       if (K != 0) {
@@ -657,17 +670,19 @@ __device__ __forceinline__ void encode_pass(const CBatch& b, uint32_t* s_scan, u
       // stage the kept bytes of each value, most significant first: q holds
       // only its top nb bytes, so after the byte swap the value's string is
       // img >> 8 ci with zero bytes above it (ci <= 3 keeps the shift < 32)
-      LanePacker pk(s_stage, tile_bytes + ex);
+      if (live) {
+        LanePacker pk(s_stage, tile_bytes + ex);
 #pragma unroll
-      for (int i = 0; i < EPL; ++i) {
-        const int ci = (int)((codes >> (2 * (EPL - 1 - i))) & 3u);
-        const bool valid = K != 0 && i < cnt_s;
-        const int Li = valid ? nb - ci : 0;
-        const U img = raw ? q[i] : byte_swap(q[i]);
-        const U sv = valid ? (U)(img >> (8 * ci)) : (U)0;
-        pk.put(sv, Li);
+        for (int i = 0; i < EPL; ++i) {
+          const int ci = (int)((codes >> (2 * (EPL - 1 - i))) & 3u);
+          const bool valid = K != 0 && i < cnt_s;
+          const int Li = valid ? nb - ci : 0;
+          const U img = raw ? q[i] : byte_swap(q[i]);
+          const U sv = valid ? (U)(img >> (8 * ci)) : (U)0;
+          pk.put(sv, Li);
+        }
+        pk.flush();
       }
-      pk.flush();
       tile_bytes += rtot;
     }
     if (threadIdx.x == 0) lookback_publish(mid_status, t, tile_bytes);
