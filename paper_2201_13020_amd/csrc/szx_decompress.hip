@@ -53,10 +53,9 @@ __global__ __launch_bounds__(256) void k_dinit(DBatch b) {
 __device__ __forceinline__ uint64_t rd64(const uint8_t* p) { return *reinterpret_cast<const uint64_t*>(p); }
 __device__ __forceinline__ uint32_t rd32(const uint8_t* p) { return *reinterpret_cast<const uint32_t*>(p); }
 
-// Mask of the top c bytes of the 24-bit leading field kept in bits 31..8.
-__device__ __forceinline__ uint32_t lead_mask(uint32_t c) {
-  return c == 0 ? 0u : (c == 1 ? 0xFF000000u : (c == 2 ? 0xFFFF0000u : 0xFFFFFF00u));
-}
+// Mask of the top c bytes (c in [0, 3]) of the 24-bit leading field kept in
+// bits 31..8, branch-free: the field's mask shifted left by 8 (3 - c).
+__device__ __forceinline__ uint32_t lead_mask(uint32_t c) { return 0xFFFFFF00u << (8u * (3u - c)); }
 
 // Composition of two leading-byte transforms packed as (S in bits 31..8, c in
 // bits 1..0): first `a`, then `b`.
@@ -99,12 +98,22 @@ __device__ __forceinline__ uint64_t lds_get<uint64_t>(const uint32_t* stage, uin
   return lds_get64(stage, off);
 }
 
-// The top c bytes of a word for c in [0, 3], branch-free: the top three
-// bytes shifted left by 8 (3 - c) (c = 0 shifts them out entirely).
+// The top c bytes of a word, from s8 = 8 c (c in [0, 3]): the complement of
+// the all-ones word shifted right by s8.
 template <typename U>
-__device__ __forceinline__ U top_bytes3(uint32_t c) {
-  constexpr U TOP3 = (U)0xFFFFFFu << (sizeof(U) * 8 - 24);
-  return (U)(TOP3 << (8u * (3u - c)));
+__device__ __forceinline__ U top_bytes_of(uint32_t s8) {
+  return (U)~((U)~(U)0 >> s8);
+}
+
+// Bytes of a decode tile's LDS stage: the tile's mid bytes at most (a value
+// stores at most its width), the 15-byte misalignment of their start and the
+// round-up to whole 16-byte chunks, then room for the unguarded reads of a
+// lane: it starts at most at the end of all stored bytes, advances at most a
+// word per value before its last read, and a read takes up to 12 bytes.
+template <typename T, int B>
+constexpr int dec_stage_words() {
+  using G = GeoD<T, B>;
+  return (G::TILE * G::SUB * (int)sizeof(T) + 32 + G::EPL * (int)sizeof(T) + 16) / 4;
 }
 
 // Previous lane's value within groups of G lanes (lanes with lig < d get
@@ -308,7 +317,6 @@ __device__ __forceinline__ void decode_tile(const FieldD& a, uint32_t t, uint32_
   using G = GeoD<T, B>;
   constexpr int EPL = G::EPL, LPB = G::LPB, TB = G::TB, SUB = G::SUB, TBLK = G::TBLK;
   constexpr int BYTES = Traits<T>::BYTES;
-  constexpr int STAGE_WORDS = (G::TILE * SUB * BYTES + 32) / 4 + 8;
 
   const StreamInfo h = read_header<BYTES, B>(a);
   if (!h.ok) return;  // k_dindex reported it
@@ -395,15 +403,22 @@ __device__ __forceinline__ void decode_tile(const FieldD& a, uint32_t t, uint32_
         for (int j = 0; j < EPL / 4; ++j) c = (c << 8) | cp[j];
       }
     }
-    c = K > 0 ? c : 0u;
+    // stored bytes of the lane: nb per live value less its code. Codes of
+    // values past the end are cleared; a code above nb marks the stream bad
+    // and its row is then read as if all codes were 0, which keeps every
+    // offset within the stage.
+    const int cn = cnt[s];
     uint32_t lb = 0;
-#pragma unroll
-    for (int i = 0; i < EPL; ++i) {
-      const int ci = (int)((c >> (2 * (EPL - 1 - i))) & 3u);
-      const bool live = i < cnt[s];
-      bad = bad || (K > 0 && live && ci > nb);
-      const int L = K < 0 ? BYTES : (ci > nb ? 0 : nb - ci);
-      lb += (live && K != 0) ? (uint32_t)L : 0u;
+    if (K > 0) {
+      c &= (uint32_t)(((1ull << (2 * cn)) - 1) << (2 * (EPL - cn)));
+      const uint32_t hi = c & 0xAAAAAAAAu, lo = c & 0x55555555u;
+      const bool over = (nb == 1 && hi != 0) || (nb == 2 && (lo & (hi >> 1)) != 0);
+      bad = bad || over;
+      c = over ? 0u : c;
+      lb = (uint32_t)(nb * cn) - (uint32_t)(__popc(c & 0x55555555u) + 2 * __popc(c & 0xAAAAAAAAu));
+    } else {
+      c = 0;
+      lb = K < 0 ? (uint32_t)(BYTES * cn) : 0u;
     }
     Ks[s] = K;
     cw[s] = c;
@@ -422,14 +437,17 @@ __device__ __forceinline__ void decode_tile(const FieldD& a, uint32_t t, uint32_
     const int K = Ks[s];
     T v[EPL];
     uint32_t o = st + off[s];
-    if (K <= 0) {
-      // constant (mu) or raw (stored bytes); o only advances for raw blocks
+    // Reads of the stage go unguarded: a lane starts at most at the end of
+    // the tile's stored bytes and advances at most a word per value, which
+    // the stage's size allows for. Values past the end of a short block read
+    // whatever lies there and are not stored; being last in their lane and
+    // block, they only reach other such values.
+    if (K == 0) {  // constant: mu
 #pragma unroll
-      for (int i = 0; i < EPL; ++i) {
-        const U raw = lds_get<U>(s_stage, o < STAGE_WORDS * 4 - 12 ? o : 0);
-        v[i] = K < 0 ? from_bits<T>(raw) : mu[s];
-        o += (K < 0 && i < cnt[s]) ? BYTES : 0;
-      }
+      for (int i = 0; i < EPL; ++i) v[i] = mu[s];
+    } else if (K < 0) {  // raw: the stored words
+#pragma unroll
+      for (int i = 0; i < EPL; ++i) v[i] = from_bits<T>(lds_get<U>(s_stage, o + (uint32_t)(i * BYTES)));
     } else {
       const int nb = bytes_of(K);
       const int sh = shift_of(K);
@@ -440,20 +458,17 @@ __device__ __forceinline__ void decode_tile(const FieldD& a, uint32_t t, uint32_
       uint32_t cm = 3;
 #pragma unroll
       for (int i = 0; i < EPL; ++i) {
-        uint32_t ci = (cw[s] >> (2 * (EPL - 1 - i))) & 3u;
-        ci = ci > (uint32_t)nb ? (uint32_t)nb : ci;
-        const bool live = i < cnt[s];
-        const uint32_t L = live ? (uint32_t)nb - ci : 0u;
-        // the word at o holds this value's L stored bytes, then whatever
+        // ci <= nb here (checked above), so the value stores nb - ci bytes
+        const uint32_t ci = (cw[s] >> (2 * (EPL - 1 - i))) & 3u;
+        const uint32_t s8 = ci << 3;
+        // the word at o holds this value's stored bytes, then whatever
         // follows; after the shift and byte swap those land below the kept
         // bytes, where `keep` clears them at the end (ci <= 3: shift < 32)
-        const U got = lds_get<U>(s_stage, o < STAGE_WORDS * 4 - 12 ? o : 0);
-        o += L;
-        const U stored = byte_swap((U)(got << (8 * ci)));
-        // values past the end of a short block act as the identity
-        const uint32_t cc = live ? ci : 3u;
-        run = (run & top_bytes3<U>(cc)) | stored;
-        cm = cc < cm ? cc : cm;
+        const U got = lds_get<U>(s_stage, o);
+        o += (uint32_t)nb - ci;
+        const U stored = byte_swap((U)(got << s8));
+        run = (run & top_bytes_of<U>(s8)) | stored;
+        cm = ci < cm ? ci : cm;
         q0[i] = run;
         cmin[i] = cm;
       }
@@ -490,7 +505,7 @@ __device__ __forceinline__ void decode_tile(const FieldD& a, uint32_t t, uint32_
       const U cfull = from_top24<U>(carry);
 #pragma unroll
       for (int i = 0; i < EPL; ++i) {
-        const U qi = (q0[i] | (cfull & top_bytes3<U>(cmin[i]))) & keep;
+        const U qi = (q0[i] | (cfull & top_bytes_of<U>(cmin[i] << 3))) & keep;
         v[i] = mu[s] + from_bits<T>((U)(qi << sh));
       }
     }
@@ -504,7 +519,7 @@ template <typename T, int B>
 __global__ __launch_bounds__(256) void k_decode(DBatch b) {
   using G = GeoD<T, B>;
   __shared__ uint32_t s_scan[G::SUB * kWavesPerWG];
-  __shared__ __align__(16) uint32_t s_stage[(G::TILE * G::SUB * Traits<T>::BYTES + 32) / 4 + 8];
+  __shared__ __align__(16) uint32_t s_stage[dec_stage_words<T, B>()];
   const uint64_t g = blockIdx.x;
   const FieldD f = field_at(b, dfield_of(b.field_dec[Traits<T>::BYTES / 8], g));
   decode_tile<T, B>(f, (uint32_t)(g - f.base_dec), s_scan, s_stage);

@@ -165,6 +165,29 @@ def test_decoder_flags_corrupt_streams():
     assert st == 0
 
 
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_decoder_flags_codes_above_kept_bytes(dtype):
+    """A code of 3 in a block that keeps only two bytes (nb = 2) is malformed:
+    the decoder reports it (and reads nothing outside its buffers)."""
+    x = np.cumsum(np.random.default_rng(3).standard_normal(20_000)).astype(dtype)
+    ref = szref.compress(x, 1e-2, "rel", 128)
+    info = sf.parse(ref)
+    from paper_2201_13020_amd import szx
+    exp = szx.inspect(ref[:96].tobytes())
+    blocks = np.nonzero(info["state"])[0]  # block of each rank
+    two = [r for r in range(info["n_nc"]) if info["K"][r] != 0xFF and (int(info["K"][r]) + 7) // 8 == 2
+           and sf.block_len(info, int(blocks[r])) == info["b"]]
+    assert len(two) > 10
+    for r, span in ((two[0], slice(None)), (two[len(two) // 2], slice(5, 6)), (two[-1], slice(31, 32))):
+        c = ref.copy()
+        row = info["offsets"]["codes"] + r * (info["b"] // 4)
+        c[row:row + info["b"] // 4][span] = 0xFF
+        y, st = gpu_decompress(c, exp)
+        assert st == 3, (r, span)
+    y, st = gpu_decompress(ref, exp)
+    assert st == 0 and same_bits(y, szref.decompress(ref))
+
+
 def test_determinism_repeated_calls():
     x = smooth(1_000_003, 8)
     a = gpu_roundtrip(x, 1e-3, "rel", 128)[0]
