@@ -614,9 +614,13 @@ __device__ __forceinline__ void encode_pass(const CBatch& b, uint32_t* s_scan, u
       int nb = 0;
       uint32_t codes = 0, lb = 0;
       const bool coded = K > 0;
+      // Without a short block (the last of a field) in the wave, no value
+      // needs a validity test: constant and absent blocks encode as zero
+      // words that keep nothing (K = 0: no kept bytes, no codes), raw blocks
+      // keep every byte with code 0.
+      const bool whole = __ballot(K != 0 && cnt_s != EPL) == 0;
       if (live) {
-        bool ok = encode_try<T, EPL>(cur.x[s], coded ? cur.cnt[s] : 0, cur.mu[s], e, coded ? K : Traits<T>::W,
-                                     coded && cur.verify[s], q);
+        bool ok = encode_try<T, EPL>(cur.x[s], coded ? cnt_s : 0, cur.mu[s], e, K, coded && cur.verify[s], q);
         if (!group_all<LPB>(ok)) {  // only coded blocks can fail
           const int K1 = kept_bits<T>(K - Traits<T>::KMIN + 1);
           bool ok1 = false;
@@ -624,30 +628,42 @@ __device__ __forceinline__ void encode_pass(const CBatch& b, uint32_t* s_scan, u
           K = group_all<LPB>(ok1) ? K1 : -1;
         }
         raw = K < 0;
-        if (raw) {
+        if (raw) {  // byte-swapped here, so that every string below is byte_swap(q) >> 8 ci
 #pragma unroll
-          for (int i = 0; i < EPL; ++i) q[i] = bits_of(cur.x[s][i]);
+          for (int i = 0; i < EPL; ++i) q[i] = byte_swap(bits_of(cur.x[s][i]));
         }
         nb = raw ? BYTES : (K > 0 ? bytes_of(K) : 0);
         U prev = lane_before<LPB, U>(q[EPL - 1]);
         prev = lig == 0 ? (U)0 : prev;
-        const uint32_t cap = (uint32_t)(nb < 3 ? nb : 3);
-        uint32_t csum = 0;
-#pragma unroll
-        for (int i = 0; i < EPL; ++i) {
-          // leading identical bytes capped at min(3, nb); a zero difference
-          // counts all bytes, which the cap turns into min(3, nb) as well. The
-          // cap is at most 24 bits, so a 64-bit word's high half decides it.
-          const U z = q[i] ^ prev;
+        // leading identical bytes capped at min(3, nb) (0 for raw blocks); a
+        // zero difference counts all bytes, which the cap turns into the cap
+        // as well. The cap is at most 24 bits, so a 64-bit word's high half
+        // decides it.
+        const uint32_t cap8 = raw ? 0u : 8u * (uint32_t)(nb < 3 ? nb : 3);
+        auto code_of = [&](U z) -> uint32_t {
           const uint32_t lz = sizeof(U) == 8 ? lead_zero_bits((uint32_t)((uint64_t)z >> 32)) : lead_zero_bits(z);
-          uint32_t ci = (lz < 8u * cap ? lz : 8u * cap) >> 3;
-          ci = (K > 0 && i < cnt_s) ? ci : 0u;
-          codes |= ci << (2 * (EPL - 1 - i));
-          csum += ci;
-          prev = q[i];
+          return (lz < cap8 ? lz : cap8) >> 3;
+        };
+        uint32_t csum = 0;
+        if (whole) {
+#pragma unroll
+          for (int i = 0; i < EPL; ++i) {
+            const uint32_t ci = code_of(q[i] ^ prev);
+            codes |= ci << (2 * (EPL - 1 - i));
+            csum += ci;
+            prev = q[i];
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < EPL; ++i) {
+            const uint32_t ci = i < cnt_s ? code_of(q[i] ^ prev) : 0u;
+            codes |= ci << (2 * (EPL - 1 - i));
+            csum += ci;
+            prev = q[i];
+          }
         }
         // stored bytes of the lane: nb per valid value less the identical ones
-        lb = K != 0 ? (uint32_t)(nb * cnt_s) - csum : 0u;
+        lb = (uint32_t)(nb * cnt_s) - csum;
       }
       uint32_t rtot;
       const uint32_t ex = wg_excl_sum<uint32_t>(lb, s_scan, rtot);
@@ -669,17 +685,24 @@ __device__ __forceinline__ void encode_pass(const CBatch& b, uint32_t* s_scan, u
       }
       // stage the kept bytes of each value, most significant first: q holds
       // only its top nb bytes, so after the byte swap the value's string is
-      // img >> 8 ci with zero bytes above it (ci <= 3 keeps the shift < 32)
+      // byte_swap(q) >> 8 ci with zero bytes above it (ci <= 3 keeps the
+      // shift < 32)
       if (live) {
         LanePacker pk(s_stage, tile_bytes + ex);
+        if (whole) {
 #pragma unroll
-        for (int i = 0; i < EPL; ++i) {
-          const int ci = (int)((codes >> (2 * (EPL - 1 - i))) & 3u);
-          const bool valid = K != 0 && i < cnt_s;
-          const int Li = valid ? nb - ci : 0;
-          const U img = raw ? q[i] : byte_swap(q[i]);
-          const U sv = valid ? (U)(img >> (8 * ci)) : (U)0;
-          pk.put(sv, Li);
+          for (int i = 0; i < EPL; ++i) {
+            const int ci = (int)((codes >> (2 * (EPL - 1 - i))) & 3u);
+            pk.put((U)(byte_swap(q[i]) >> (8 * ci)), nb - ci);
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < EPL; ++i) {
+            const int ci = (int)((codes >> (2 * (EPL - 1 - i))) & 3u);
+            const bool valid = i < cnt_s;
+            const U sv = valid ? (U)(byte_swap(q[i]) >> (8 * ci)) : (U)0;
+            pk.put(sv, valid ? nb - ci : 0);
+          }
         }
         pk.flush();
       }
