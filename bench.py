@@ -183,28 +183,37 @@ def main():
         ratios[eb] = nbytes / stream_len[eb]
     if not args.no_cpu_baseline and not args.profile:
         from oracle import szref
+        # the whole workload, repeated until about 10 s of CPU time (the
+        # first pass also checks the GPU results against the oracle)
         t_c = t_d = 0.0
-        for eb in BOUNDS:
-            t0 = time.perf_counter()
-            ref = szref.compress(x_np, eb, "rel", BLOCK)
-            t1 = time.perf_counter()
-            yref = szref.decompress(ref)
-            t2 = time.perf_counter()
-            t_c += t1 - t0
-            t_d += t2 - t1
-            gpu_stream = outs[eb][0][: stream_len[eb]].cpu().numpy()
-            assert gpu_stream.size == ref.size and np.array_equal(gpu_stream, ref), f"GPU stream differs from the oracle at eb={eb}"
-        y_last = ys[0].cpu().numpy()
-        udt = np.uint32 if w == 4 else np.uint64
-        assert np.array_equal(y_last.view(udt), yref.ravel().view(udt)), "GPU decode differs from the oracle"
+        passes = 0
+        while passes == 0 or (t_c + t_d < 10.0 and passes < 64):
+            for eb in BOUNDS:
+                t0 = time.perf_counter()
+                ref = szref.compress(x_np, eb, "rel", BLOCK)
+                t1 = time.perf_counter()
+                yref = szref.decompress(ref)
+                t2 = time.perf_counter()
+                t_c += t1 - t0
+                t_d += t2 - t1
+                if passes == 0:
+                    gpu_stream = outs[eb][0][: stream_len[eb]].cpu().numpy()
+                    assert gpu_stream.size == ref.size and np.array_equal(gpu_stream, ref), \
+                        f"GPU stream differs from the oracle at eb={eb}"
+            if passes == 0:
+                y_last = ys[0].cpu().numpy()
+                udt = np.uint32 if w == 4 else np.uint64
+                assert np.array_equal(y_last.view(udt), yref.ravel().view(udt)), "GPU decode differs from the oracle"
+            passes += 1
+        done = passes * len(BOUNDS) * nbytes
         cpu = {
-            "value": round(len(BOUNDS) * nbytes / (t_c + t_d) / 1e9, 4),
+            "value": round(done / (t_c + t_d) / 1e9, 4),
             "unit": "GB/s",
             "cores": 1,
             "kind": "oracle",
-            "sample": f"whole workload once: {field['desc']}, REL {', '.join(map(str, BOUNDS))}, "
-                      f"compress + decompress each, single thread; compress {len(BOUNDS) * nbytes / t_c / 1e6:.0f} MB/s, "
-                      f"decompress {len(BOUNDS) * nbytes / t_d / 1e6:.0f} MB/s",
+            "sample": f"whole workload {passes} times: {field['desc']}, REL {', '.join(map(str, BOUNDS))}, "
+                      f"compress + decompress each, single thread; compress {done / t_c / 1e6:.0f} MB/s, "
+                      f"decompress {done / t_d / 1e6:.0f} MB/s",
             "seconds": round(t_c + t_d, 3),
         }
 

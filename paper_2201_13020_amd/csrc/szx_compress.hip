@@ -93,6 +93,18 @@ __device__ __forceinline__ int load_run(const T* __restrict__ x, uint64_t i0, ui
   return cnt;
 }
 
+// Load the first cnt of EPL consecutive values at x + i0 (aligned to EPL);
+// the others are zero.
+template <typename T, int EPL>
+__device__ __forceinline__ void load_count(const T* __restrict__ x, uint32_t i0, int cnt, T (&v)[EPL]) {
+  if (cnt == EPL) {
+    load_run<T, EPL>(x, i0, (uint64_t)i0 + EPL, v);
+    return;
+  }
+#pragma unroll
+  for (int i = 0; i < EPL; ++i) v[i] = i < cnt ? x[i0 + i] : (T)0;
+}
+
 template <int G, typename U>
 __device__ __forceinline__ U group_min(U v) {
 #pragma unroll
@@ -517,23 +529,56 @@ __device__ __forceinline__ void tile_load(TileIn<T, B>& in, uint32_t t, const T*
   const int g = threadIdx.x / LPB, lig = threadIdx.x % LPB;
   in.r0 = enc_r0[t];
   uint32_t first[SUB];
+  if constexpr (sizeof(T) == 4) {
+    // the tile's first block and value (wave-uniform), its block and value
+    // counts; lanes index from them with 32-bit offsets. (For float64 the
+    // same form measured slower: it left the encoder spilling registers.)
+    const uint64_t kb = (uint64_t)t * TBLK;
+    const uint32_t nblk_t = (uint32_t)std::min<uint64_t>(nblk - kb, (uint64_t)TBLK);
+    const uint32_t nval_t = (uint32_t)std::min<uint64_t>(n - kb * B, (uint64_t)TBLK * B);
+    const T* x_t = x + kb * B;
+    const T* mus_t = mus + kb;
+    const uint8_t* plan_t = plan + kb;
 #pragma unroll
-  for (int s = 0; s < SUB; ++s) {
-    const uint64_t k = (uint64_t)t * TBLK + (uint64_t)s * TB + g;
-    T mu = (T)0;
-    uint32_t pb = 0;
-    if (k < nblk) {
-      mu = mus[k];
-      pb = plan[k];
+    for (int s = 0; s < SUB; ++s) {
+      const uint32_t lk = (uint32_t)(s * TB + g);
+      const bool inb = lk < nblk_t;
+      T mu = (T)0;
+      uint32_t pb = 0;
+      if (inb) {
+        mu = mus_t[lk];
+        pb = plan_t[lk];
+      }
+      const int K = pb == 0xFFu ? -1 : (int)(pb & 0x7Fu);
+      in.mu[s] = mu;
+      in.K[s] = K;
+      in.verify[s] = (pb & 0x80u) != 0 && pb != 0xFFu;
+      // values from this lane's first one to the tile's end (constant blocks load none)
+      const int rem = (int)nval_t - (int)(lk * B) - lig * EPL;
+      const int cnt = (inb && K != 0) ? (rem < 0 ? 0 : (rem > EPL ? EPL : rem)) : 0;
+      in.cnt[s] = cnt;
+      load_count<T, EPL>(x_t, lk * B + (uint32_t)(lig * EPL), cnt, in.x[s]);
+      first[s] = (lig == 0 && K != 0) ? 1u : 0u;
     }
-    const int K = pb == 0xFFu ? -1 : (int)(pb & 0x7Fu);
-    in.mu[s] = mu;
-    in.K[s] = K;
-    in.verify[s] = (pb & 0x80u) != 0 && pb != 0xFFu;
-    const uint64_t nk = (k < nblk && K != 0) ? std::min<uint64_t>((uint64_t)B, n - k * B) : 0;
-    in.cnt[s] = (int)((uint64_t)lig * EPL >= nk ? 0 : std::min<uint64_t>(EPL, nk - (uint64_t)lig * EPL));
-    load_run<T, EPL>(x, k * B + (uint64_t)lig * EPL, k * B + nk, in.x[s]);
-    first[s] = (lig == 0 && K != 0) ? 1u : 0u;
+  } else {
+#pragma unroll
+    for (int s = 0; s < SUB; ++s) {
+      const uint64_t k = (uint64_t)t * TBLK + (uint64_t)s * TB + g;
+      T mu = (T)0;
+      uint32_t pb = 0;
+      if (k < nblk) {
+        mu = mus[k];
+        pb = plan[k];
+      }
+      const int K = pb == 0xFFu ? -1 : (int)(pb & 0x7Fu);
+      in.mu[s] = mu;
+      in.K[s] = K;
+      in.verify[s] = (pb & 0x80u) != 0 && pb != 0xFFu;
+      const uint64_t nk = (k < nblk && K != 0) ? std::min<uint64_t>((uint64_t)B, n - k * B) : 0;
+      in.cnt[s] = (int)((uint64_t)lig * EPL >= nk ? 0 : std::min<uint64_t>(EPL, nk - (uint64_t)lig * EPL));
+      load_run<T, EPL>(x, k * B + (uint64_t)lig * EPL, k * B + nk, in.x[s]);
+      first[s] = (lig == 0 && K != 0) ? 1u : 0u;
+    }
   }
   uint32_t tot[SUB];
   wg_excl_scan_multi<SUB>(first, in.rank, tot, s_scan);

@@ -341,22 +341,36 @@ __device__ __forceinline__ void decode_tile(const FieldD& a, uint32_t t, uint32_
   const uint64_t src = h.sec.mid + m0;
   const uint32_t st = (uint32_t)(src & 15u);
   {
+    // 64-bit positions stay with the tile (wave-uniform); lanes use 32-bit
+    // offsets from them
     const uint64_t src0 = src - st;
+    const uint8_t* base = in + src0;
+    const uint64_t left = a.in_bytes > src0 ? a.in_bytes - src0 : 0;
+    const uint32_t avail = (uint32_t)std::min<uint64_t>(left, 0xFFFFFFFFull);
     const uint32_t nchunk = (st + tile_bytes + 15) / 16;
     for (uint32_t ch = threadIdx.x; ch < nchunk; ch += kWG) {
-      const uint64_t gpos = src0 + (uint64_t)ch * 16;
+      const uint32_t off = ch * 16;
       uint4 u = make_uint4(0, 0, 0, 0);
-      if (gpos + 16 <= a.in_bytes) {
-        u = *reinterpret_cast<const uint4*>(in + gpos);
+      if (off + 16 <= avail) {
+        u = *reinterpret_cast<const uint4*>(base + off);
       } else {
         uint32_t wv[4] = {0, 0, 0, 0};
-        for (int bq = 0; bq < 16; ++bq)
-          if (gpos + bq < a.in_bytes) wv[bq >> 2] |= (uint32_t)in[gpos + bq] << ((bq & 3) * 8);
+        for (uint32_t bq = 0; bq < 16; ++bq)
+          if (off + bq < avail) wv[bq >> 2] |= (uint32_t)base[off + bq] << ((bq & 3) * 8);
         u = make_uint4(wv[0], wv[1], wv[2], wv[3]);
       }
       reinterpret_cast<uint4*>(s_stage)[ch] = u;
     }
   }
+
+  // the tile's first block and value (wave-uniform), its block and value
+  // counts; lanes index from them with 32-bit offsets
+  const uint64_t kb = (uint64_t)t * TBLK;
+  const uint32_t nblk_t = (uint32_t)std::min<uint64_t>(a.nblk - kb, (uint64_t)TBLK);
+  const uint32_t nval_t = (uint32_t)std::min<uint64_t>(a.n - kb * B, (uint64_t)TBLK * B);
+  const uint8_t* state_t = in + h.sec.state + (kb >> 3);  // a tile owns whole state bytes
+  const T* mus_t = mus + kb;
+  T* y_t = y + kb * B;
 
   // ranks of the tile's non-constant blocks, their K bytes and codes
   bool nc[SUB];
@@ -365,12 +379,13 @@ __device__ __forceinline__ void decode_tile(const FieldD& a, uint32_t t, uint32_
   T mu[SUB];
 #pragma unroll
   for (int s = 0; s < SUB; ++s) {
-    const uint64_t k = (uint64_t)t * TBLK + (uint64_t)s * TB + g;
-    const bool inb = k < a.nblk;
-    nc[s] = inb && ((in[h.sec.state + (k >> 3)] >> (k & 7)) & 1u);
-    mu[s] = inb ? mus[k] : (T)0;
-    const uint64_t nk = inb ? std::min<uint64_t>((uint64_t)B, a.n - k * B) : 0;
-    cnt[s] = (int)((uint64_t)lig * EPL >= nk ? 0 : std::min<uint64_t>(EPL, nk - (uint64_t)lig * EPL));
+    const uint32_t lk = (uint32_t)(s * TB + g);
+    const bool inb = lk < nblk_t;
+    nc[s] = inb && ((state_t[lk >> 3] >> (lk & 7)) & 1u);
+    mu[s] = inb ? mus_t[lk] : (T)0;
+    // values from this lane's first one to the tile's end
+    const int rem = (int)nval_t - (int)(lk * B) - lig * EPL;
+    cnt[s] = inb ? (rem < 0 ? 0 : (rem > EPL ? EPL : rem)) : 0;
     first_of[s] = (lig == 0 && nc[s]) ? 1u : 0u;
   }
   uint32_t rk[SUB], rtot[SUB];
@@ -378,13 +393,17 @@ __device__ __forceinline__ void decode_tile(const FieldD& a, uint32_t t, uint32_
   int Ks[SUB];       // kept bits; -1 raw; 0 constant or unusable
   uint32_t cw[SUB];  // this lane's EPL codes, first value in the top bits
   uint32_t nbytes[SUB];
+  // ranks from r0 on, 32-bit within the tile
+  const uint32_t nnc_t = (uint32_t)std::min<uint64_t>(h.n_nc > r0 ? h.n_nc - r0 : 0, (uint64_t)TBLK);
+  const uint8_t* kbytes_t = in + h.sec.kbytes + r0;
+  const uint8_t* codes_t = in + h.sec.codes + r0 * (B / 4);
 #pragma unroll
   for (int s = 0; s < SUB; ++s) {
     // the group's first lane counted its block; the others see it counted
-    const uint64_t r = r0 + rk[s] - ((lig != 0 && nc[s]) ? 1u : 0u);
-    const bool have = nc[s] && r < h.n_nc;
-    bad = bad || (nc[s] && r >= h.n_nc);
-    int K = have ? (int)in[h.sec.kbytes + r] : 0;
+    const uint32_t rl = rk[s] - ((lig != 0 && nc[s]) ? 1u : 0u);
+    const bool have = nc[s] && rl < nnc_t;
+    bad = bad || (nc[s] && rl >= nnc_t);
+    int K = have ? (int)kbytes_t[rl] : 0;
     if (K == kRawK) {
       K = -1;
     } else if (have && (K < Traits<T>::KMIN || K > Traits<T>::W)) {
@@ -394,7 +413,7 @@ __device__ __forceinline__ void decode_tile(const FieldD& a, uint32_t t, uint32_
     const int nb = K > 0 ? bytes_of(K) : 0;
     uint32_t c = 0;
     if (have) {  // loaded beside K, used only for a coded block
-      const uint8_t* cp = in + h.sec.codes + r * (B / 4) + (uint64_t)lig * (EPL / 4);
+      const uint8_t* cp = codes_t + rl * (B / 4) + (uint32_t)lig * (EPL / 4);
       if constexpr (EPL == 8) {
         const uint32_t v16 = *reinterpret_cast<const uint16_t*>(cp);
         c = ((v16 & 0xFFu) << 8) | (v16 >> 8);
@@ -509,8 +528,7 @@ __device__ __forceinline__ void decode_tile(const FieldD& a, uint32_t t, uint32_
         v[i] = mu[s] + from_bits<T>((U)(qi << sh));
       }
     }
-    const uint64_t k = (uint64_t)t * TBLK + (uint64_t)s * TB + g;
-    if (cnt[s] > 0) store_run<T, EPL>(y, k * B + (uint64_t)lig * EPL, cnt[s], v);
+    if (cnt[s] > 0) store_run<T, EPL>(y_t, (uint32_t)((s * TB + g) * B + lig * EPL), cnt[s], v);
   }
   if (__ballot(bad) != 0 && lane == 0) atomicMax(a.status, kStatusCorrupt);
 }
