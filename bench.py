@@ -515,31 +515,39 @@ def bench_batch(args):
         from oracle import szref
         r = np.random.default_rng(5)
         pick = sorted(r.choice(len(xs), size=min(args.cpu_sample_fields, len(xs)), replace=False).tolist())
+        hosts = [xs[i].cpu().numpy() for i in pick]
+        # the sample, repeated until about 10 s of CPU time (the first pass
+        # also checks the batch output against the oracle)
         tc = td = 0.0
         sb = 0
-        for i in pick:
-            xh = xs[i].cpu().numpy()
-            t1 = time.perf_counter()
-            ref = szref.compress(xh, ebs[i], "rel", BLOCK)
-            t2 = time.perf_counter()
-            yref = szref.decompress(ref)
-            t3 = time.perf_counter()
-            tc += t2 - t1
-            td += t3 - t2
-            sb += xh.nbytes
-            assert np.array_equal(cb.outs[i][:lens[i]].cpu().numpy(), ref), f"field {i} differs from the oracle"
-            udt = np.uint32 if xh.itemsize == 4 else np.uint64
-            yb = db.outs[i].cpu().numpy()
-            assert np.array_equal(yb.view(udt), yref.ravel().view(udt)), f"field {i} decode differs from the oracle"
-        cpu = {"value": round(2 * sb / (tc + td) / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
-               "sample": f"{len(pick)} fields of the batch drawn at random ({sb / 2**20:.0f} MiB), compress + "
-                         f"decompress each, single thread; matched the batch output byte for byte",
+        passes = 0
+        while passes == 0 or (tc + td < 10.0 and passes < 256):
+            for i, xh in zip(pick, hosts):
+                t1 = time.perf_counter()
+                ref = szref.compress(xh, ebs[i], "rel", BLOCK)
+                t2 = time.perf_counter()
+                yref = szref.decompress(ref)
+                t3 = time.perf_counter()
+                tc += t2 - t1
+                td += t3 - t2
+                sb += xh.nbytes
+                if passes == 0:
+                    assert np.array_equal(cb.outs[i][:lens[i]].cpu().numpy(), ref), f"field {i} differs from the oracle"
+                    udt = np.uint32 if xh.itemsize == 4 else np.uint64
+                    yb = db.outs[i].cpu().numpy()
+                    assert np.array_equal(yb.view(udt), yref.ravel().view(udt)), \
+                        f"field {i} decode differs from the oracle"
+            passes += 1
+        cpu = {"value": round(sb / (tc + td) / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+               "sample": f"{len(pick)} fields of the batch drawn at random ({sb / passes / 2**20:.0f} MiB), "
+                         f"compress + decompress each, {passes} times, single thread; matched the batch output "
+                         f"byte for byte",
                "seconds": round(tc + td, 3)}
         _log(f"oracle sample of {len(pick)} fields matched")
 
     result = {
         "metric": "compress & decompress GB/s (uncompressed) and % of HBM peak; ratio",
-        "value": round(2 * total / ms_step / 1e6, 2),
+        "value": round(total / ms_step / 1e6, 2),
         "unit": "GB/s",
         "n_gpus": 1,
         "steps": steps,
