@@ -54,7 +54,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile", action="store_true",
                     help="short eager run for profilers: no CPU baseline, no instrumented pass, plus a plain 256 MiB copy whose HBM counters scale the others")
-    ap.add_argument("--field", type=str, default="cfg2", choices=sorted(FIELDS) + ["cfg4", "cfg5"],
+    ap.add_argument("--io-dir", type=str, default=None, help="io: directory for the stream files (default: a new temporary one)")
+    ap.add_argument("--field", type=str, default="cfg2", choices=sorted(FIELDS) + ["cfg4", "cfg5", "io"],
                     help="cfg4: the many-field batch (batched launches vs per-field calls); "
                          "cfg5: the serving loop (continuous batching vs serial FIFO)")
     ap.add_argument("--batch-fields", type=int, default=4096, help="cfg4: number of fields")
@@ -133,6 +134,8 @@ def main():
         return bench_batch(args)
     if args.field == "cfg5":
         return bench_serve(args)
+    if args.field == "io":
+        return bench_io(args)
     dev = torch.device("cuda:0")
     global BOUNDS
     field = FIELDS[args.field]
@@ -663,6 +666,121 @@ def bench_serve(args):
             "policies": out,
             "p99_ms_ratio_serial_over_batching": {lv: round(sf[lv]["p99_ms"] / cb[lv]["p99_ms"], 2) for lv in sf},
         },
+    }
+    print(json.dumps(result), flush=True)
+
+
+
+def _mount_of(path):
+    """(mount point, filesystem type) holding path, from /proc/mounts."""
+    best = ("", "unknown")
+    try:
+        real = os.path.realpath(path)
+        for line in open("/proc/mounts"):
+            parts = line.split()
+            if len(parts) >= 3 and (real == parts[1] or real.startswith(parts[1].rstrip("/") + "/")):
+                if len(parts[1]) > len(best[0]):
+                    best = (parts[1], parts[2])
+    except OSError:
+        pass
+    return best
+
+
+def bench_io(args):
+    """Dumping and loading a field through files, with and without
+    compression: the single-node counterpart of the paper's dumping/loading
+    breakdown (Sec. VI). Dump = compress on the GPU + write the stream to a
+    file; load = read the file into device memory + decompress. Raw = the
+    uncompressed field written and read the same way. Each leg is timed on its
+    own (device synchronised around it), the median of --steps repetitions.
+    Writes go through the page cache, and a second set flushes every file to
+    storage (fsync); reads come back from the page cache (the files were just
+    written and nothing evicts them)."""
+    import shutil
+    import statistics
+    import tempfile
+    import numpy as np
+    import torch
+    from paper_2201_13020_amd import synth, szx
+
+    field = FIELDS["cfg2"]
+    shape = field["shape"]
+    x_np = synth.make("cfg2")
+    x = torch.from_numpy(x_np).cuda()
+    nbytes = x.numel() * x.element_size()
+    own_dir = args.io_dir is None
+    d = tempfile.mkdtemp(prefix="szx_io_") if own_dir else args.io_dir
+    mount, fstype = _mount_of(d)
+    reps = max(1, min(args.steps, 5))
+    _log(f"io: {nbytes / 1e6:.0f} MB field, files under {d} ({fstype} at {mount}), {reps} repetitions")
+
+    def timed(fn):
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return statistics.median(ts)
+
+    rows = {}
+    try:
+        raw_path = os.path.join(d, "raw.bin")
+        for durable in (False, True):
+            tag = "fsync" if durable else "page_cache"
+            raw_w = timed(lambda: szx.file_write(raw_path, x, durable=durable))
+            back = torch.empty_like(x)
+            raw_r = timed(lambda: szx.file_read(raw_path, out=back))
+            assert torch.equal(back, x)
+            rows[tag] = {"raw": {"write_ms": round(raw_w * 1e3, 3), "read_ms": round(raw_r * 1e3, 3),
+                                 "dump_GBps": round(nbytes / raw_w / 1e9, 2),
+                                 "load_GBps": round(nbytes / raw_r / 1e9, 2)}}
+            for eb in field["bounds"]:
+                out, size = szx.compress(x, eb, "rel", BLOCK)
+                torch.cuda.synchronize()
+                n = int(size.cpu().view(torch.int64).item())
+                ws = torch.empty(szx.workspace_size(torch.float32, shape, eb, "rel", BLOCK), dtype=torch.uint8,
+                                 device="cuda")
+                t_c = timed(lambda: szx.compress(x, eb, "rel", BLOCK, out=out, out_size=size, ws=ws))
+                path = os.path.join(d, f"s{eb}.szx")
+                t_w = timed(lambda: szx.file_write(path, out, nbytes=n, durable=durable))
+                sbuf = torch.empty(n, dtype=torch.uint8, device="cuda")
+                t_r = timed(lambda: szx.file_read(path, out=sbuf))
+                params = dict(dtype=torch.float32, dims=shape, block=BLOCK)
+                y, st = szx.decompress(sbuf, n, params)
+                t_d = timed(lambda: szx.decompress(sbuf, n, params, out=y, status=st, ws=ws))
+                assert int(st.cpu().view(torch.int32).item()) == 0 and torch.equal(sbuf, out[:n])
+                err = float((y.reshape(-1).double() - x.reshape(-1).double()).abs().max())
+                dump, load = t_c + t_w, t_r + t_d
+                rows[tag][str(eb)] = {
+                    "ratio": round(nbytes / n, 4), "compress_ms": round(t_c * 1e3, 3), "write_ms": round(t_w * 1e3, 3),
+                    "read_ms": round(t_r * 1e3, 3), "decompress_ms": round(t_d * 1e3, 3),
+                    "dump_GBps": round(nbytes / dump / 1e9, 2), "load_GBps": round(nbytes / load / 1e9, 2),
+                    "dump_speedup_vs_raw": round(raw_w / dump, 2), "load_speedup_vs_raw": round(raw_r / load, 2),
+                    "max_abs_error": err}
+                _log(f"io {tag} eb={eb}: dump {dump * 1e3:.2f} ms (raw {raw_w * 1e3:.2f}), "
+                     f"load {load * 1e3:.2f} ms (raw {raw_r * 1e3:.2f})")
+    finally:
+        if own_dir:
+            shutil.rmtree(d, ignore_errors=True)
+    mid = rows["fsync"][str(1e-3)]
+    result = {
+        "metric": "dump + load GB/s of uncompressed bytes (compress + write, read + decompress)",
+        "value": round(2 * nbytes / ((mid["compress_ms"] + mid["write_ms"] + mid["read_ms"] + mid["decompress_ms"]) / 1e3) / 1e9, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": reps,
+        "warmup": 0,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"100x500x500 float32 turbulence field dumped to and loaded from files on {fstype}, "
+                               f"REL 1e-2/1e-3/1e-4, block 128; value: REL 1e-3 with fsync",
+                   "filesystem": fstype, "parallelism": "single GPU"},
+        "detail": rows,
     }
     print(json.dumps(result), flush=True)
 

@@ -56,7 +56,8 @@ typedef enum {
   SZ_ECORRUPT = 3,     /* stream failed validation (sz_inspect, or *d_status) */
   SZ_EDEVICE = 4,      /* a HIP call failed; see sz_last_error() */
   SZ_ENOMEM = 5,       /* reserved */
-  SZ_EUNSUPPORTED = 6  /* parameters beyond this build's limits */
+  SZ_EUNSUPPORTED = 6, /* parameters beyond this build's limits */
+  SZ_EIO = 7           /* a file operation failed (szx_io.h); see sz_last_error() */
 } sz_status;
 
 /* Parameters of one field. Dims are metadata: blocks run over the row-major

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libszx.so")
 SZ_F32, SZ_F64 = 0, 1
 SZ_ABS, SZ_REL = 0, 1
 STATUS = {0: "SZ_OK", 1: "SZ_EINVAL", 2: "SZ_ENOSPC", 3: "SZ_ECORRUPT", 4: "SZ_EDEVICE",
-          5: "SZ_ENOMEM", 6: "SZ_EUNSUPPORTED"}
+          5: "SZ_ENOMEM", 6: "SZ_EUNSUPPORTED", 7: "SZ_EIO"}
 HEADER_BYTES = 96
 
 
@@ -92,6 +92,12 @@ def lib():
         L.sz_batch_run.restype = ctypes.c_int
         L.sz_batch_destroy.argtypes = [vp]
         L.sz_batch_destroy.restype = None
+        L.sz_file_write.argtypes = [ctypes.c_char_p, vp, u64, ctypes.c_int, vp]
+        L.sz_file_write.restype = ctypes.c_int
+        L.sz_file_size.argtypes = [ctypes.c_char_p, ctypes.POINTER(u64)]
+        L.sz_file_size.restype = ctypes.c_int
+        L.sz_file_read.argtypes = [ctypes.c_char_p, vp, u64, ctypes.POINTER(u64), vp]
+        L.sz_file_read.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -354,3 +360,44 @@ def decompress_batch(streams, nbytes, expected, outs=None, statuses=None, ws=Non
     _check(lib().sz_batch_create_decompress(arr, n, _ptr(ws), ws.numel(), ctypes.byref(h)),
            "sz_batch_create_decompress")
     return Batch(h, ws, (list(streams), arr), outs=outs, statuses=statuses)
+
+
+# ------------------------------------------------------------ stream files --
+
+def file_write(path, data, nbytes=None, durable=False, stream=None):
+    """Write the first nbytes bytes of the contiguous tensor `data` (device or
+    host; default: all of it) to the file at path, once the work queued on
+    `stream` (default: torch's current stream, for a device tensor) has
+    finished. Blocks until the bytes are in the file; durable=True also
+    flushes them to storage (fsync)."""
+    if not data.is_contiguous():
+        raise ValueError("data must be contiguous")
+    total = data.numel() * data.element_size()
+    n = total if nbytes is None else int(nbytes)
+    if n < 0 or n > total:
+        raise ValueError(f"nbytes {n} outside [0, {total}]")
+    sh = _stream_handle(stream) if data.is_cuda else ctypes.c_void_p(None)
+    _check(lib().sz_file_write(os.fsencode(path), _ptr(data) if total else None, n, 1 if durable else 0, sh),
+           "sz_file_write")
+
+
+def file_size(path):
+    """Size in bytes of the file at path."""
+    n = ctypes.c_uint64()
+    _check(lib().sz_file_size(os.fsencode(path), ctypes.byref(n)), "sz_file_size")
+    return int(n.value)
+
+
+def file_read(path, out=None, device="cuda", stream=None):
+    """Read the whole file at path into `out` (a contiguous tensor with room
+    for it) or into a new uint8 tensor on `device`. The copies are complete on
+    return. Returns (tensor, bytes read)."""
+    if out is None:
+        out = torch.empty(max(file_size(path), 1), dtype=torch.uint8, device=device)
+    if not out.is_contiguous():
+        raise ValueError("out must be contiguous")
+    got = ctypes.c_uint64()
+    sh = _stream_handle(stream) if out.is_cuda else ctypes.c_void_p(None)
+    _check(lib().sz_file_read(os.fsencode(path), _ptr(out), out.numel() * out.element_size(), ctypes.byref(got), sh),
+           "sz_file_read")
+    return out, int(got.value)

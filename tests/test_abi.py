@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADERS = [os.path.join(ROOT, "include", h) for h in ("szx.h", "szx_server.h")]
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("szx.h", "szx_server.h", "szx_io.h")]
 
 
 def declared_functions():
