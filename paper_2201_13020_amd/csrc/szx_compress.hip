@@ -500,15 +500,55 @@ __device__ __forceinline__ void copy_out(uint8_t* __restrict__ out, uint64_t dst
   }
 }
 
+// Per-row plan of a tile's blocks as one lane sees them: K (-1 raw, 0
+// constant or no block, else kept bits), whether the values need verifying,
+// how many values the lane holds, and the rank of the row's block among the
+// tile's non-constant ones. For float64 the four are packed into one word
+// per row (K + 1 in bits 0-6, verify in bit 7, the count in bits 8-12, the
+// rank from bit 13): that encoder is at its register cap and spills
+// otherwise; for float32 plain fields measured faster.
+template <typename T, int B, bool PACK = (sizeof(T) == 8)>
+struct RowPlan;
+
+template <typename T, int B>
+struct RowPlan<T, B, false> {
+  static constexpr int SUB = Geo<T, B>::SUB;
+  int K_[SUB], cnt_[SUB];
+  bool verify_[SUB];
+  uint32_t rank_[SUB];
+  __device__ __forceinline__ void set(int s, int K, bool verify, int cnt) {
+    K_[s] = K;
+    verify_[s] = verify;
+    cnt_[s] = cnt;
+  }
+  __device__ __forceinline__ void set_rank(int s, uint32_t r) { rank_[s] = r; }
+  __device__ __forceinline__ int K(int s) const { return K_[s]; }
+  __device__ __forceinline__ bool verify(int s) const { return verify_[s]; }
+  __device__ __forceinline__ int cnt(int s) const { return cnt_[s]; }
+  __device__ __forceinline__ uint32_t rank(int s) const { return rank_[s]; }
+};
+
+template <typename T, int B>
+struct RowPlan<T, B, true> {
+  static constexpr int SUB = Geo<T, B>::SUB;
+  static_assert(Geo<T, B>::EPL <= 31 && Geo<T, B>::TBLK <= (1 << 19), "packed row fields overflow");
+  uint32_t meta[SUB];
+  __device__ __forceinline__ void set(int s, int K, bool verify, int cnt) {
+    meta[s] = (uint32_t)(K + 1) | (verify ? 0x80u : 0u) | ((uint32_t)cnt << 8);
+  }
+  __device__ __forceinline__ void set_rank(int s, uint32_t r) { meta[s] |= r << 13; }
+  __device__ __forceinline__ int K(int s) const { return (int)(meta[s] & 0x7Fu) - 1; }
+  __device__ __forceinline__ bool verify(int s) const { return (meta[s] >> 7) & 1u; }
+  __device__ __forceinline__ int cnt(int s) const { return (int)((meta[s] >> 8) & 31u); }
+  __device__ __forceinline__ uint32_t rank(int s) const { return meta[s] >> 13; }
+};
+
 // What a workgroup holds of one tile between its loads and its encoding.
 template <typename T, int B>
 struct TileIn {
   T x[Geo<T, B>::SUB][Geo<T, B>::EPL];
   T mu[Geo<T, B>::SUB];
-  int K[Geo<T, B>::SUB];  // plan: -1 raw, 0 constant or no block, else kept bits
-  bool verify[Geo<T, B>::SUB];
-  int cnt[Geo<T, B>::SUB];
-  uint32_t rank[Geo<T, B>::SUB];  // rank of the row's block among the tile's non-constant ones
+  RowPlan<T, B> row;
   uint64_t r0;                    // rank of the tile's first non-constant block
   uint32_t field;                 // batch entry
   uint32_t tile;                  // tile within the field
@@ -551,12 +591,10 @@ __device__ __forceinline__ void tile_load(TileIn<T, B>& in, uint32_t t, const T*
       }
       const int K = pb == 0xFFu ? -1 : (int)(pb & 0x7Fu);
       in.mu[s] = mu;
-      in.K[s] = K;
-      in.verify[s] = (pb & 0x80u) != 0 && pb != 0xFFu;
       // values from this lane's first one to the tile's end (constant blocks load none)
       const int rem = (int)nval_t - (int)(lk * B) - lig * EPL;
       const int cnt = (inb && K != 0) ? (rem < 0 ? 0 : (rem > EPL ? EPL : rem)) : 0;
-      in.cnt[s] = cnt;
+      in.row.set(s, K, (pb & 0x80u) != 0 && pb != 0xFFu, cnt);
       load_count<T, EPL>(x_t, lk * B + (uint32_t)(lig * EPL), cnt, in.x[s]);
       first[s] = (lig == 0 && K != 0) ? 1u : 0u;
     }
@@ -572,19 +610,18 @@ __device__ __forceinline__ void tile_load(TileIn<T, B>& in, uint32_t t, const T*
       }
       const int K = pb == 0xFFu ? -1 : (int)(pb & 0x7Fu);
       in.mu[s] = mu;
-      in.K[s] = K;
-      in.verify[s] = (pb & 0x80u) != 0 && pb != 0xFFu;
       const uint64_t nk = (k < nblk && K != 0) ? std::min<uint64_t>((uint64_t)B, n - k * B) : 0;
-      in.cnt[s] = (int)((uint64_t)lig * EPL >= nk ? 0 : std::min<uint64_t>(EPL, nk - (uint64_t)lig * EPL));
+      const int cnt = (int)((uint64_t)lig * EPL >= nk ? 0 : std::min<uint64_t>(EPL, nk - (uint64_t)lig * EPL));
+      in.row.set(s, K, (pb & 0x80u) != 0 && pb != 0xFFu, cnt);
       load_run<T, EPL>(x, k * B + (uint64_t)lig * EPL, k * B + nk, in.x[s]);
       first[s] = (lig == 0 && K != 0) ? 1u : 0u;
     }
   }
-  uint32_t tot[SUB];
-  wg_excl_scan_multi<SUB>(first, in.rank, tot, s_scan);
+  uint32_t tot[SUB], rank[SUB];
+  wg_excl_scan_multi<SUB>(first, rank, tot, s_scan);
   // the group's first lane counted its block; the others see it counted
 #pragma unroll
-  for (int s = 0; s < SUB; ++s) in.rank[s] -= (lig != 0 && in.K[s] != 0) ? 1u : 0u;
+  for (int s = 0; s < SUB; ++s) in.row.set_rank(s, rank[s] - ((lig != 0 && in.row.K(s) != 0) ? 1u : 0u));
 }
 
 // The encode pass for the tiles of element type T: persistent workgroups take
@@ -647,14 +684,14 @@ __device__ __forceinline__ void encode_pass(const CBatch& b, uint32_t* s_scan, u
 #pragma unroll
     for (int s = 0; s < SUB; ++s) {
       U q[EPL];
-      int K = cur.K[s];
+      int K = cur.row.K(s);
       // a wave whose blocks of this row are all constant (or past the end)
       // stores nothing: it skips to the row's offset scan, which every wave
       // joins (the vote is wave-uniform, so the branch is too). Only the
       // 64-bit words pay enough per row for the skip to win; for float32 it
       // measured no faster and the branch is left out.
       const bool live = sizeof(T) == 4 || __ballot(K != 0) != 0;
-      const int cnt_s = cur.cnt[s];
+      const int cnt_s = cur.row.cnt(s);
       bool raw = false;
       int nb = 0;
       uint32_t codes = 0, lb = 0;
@@ -665,11 +702,11 @@ __device__ __forceinline__ void encode_pass(const CBatch& b, uint32_t* s_scan, u
       // keep every byte with code 0.
       const bool whole = __ballot(K != 0 && cnt_s != EPL) == 0;
       if (live) {
-        bool ok = encode_try<T, EPL>(cur.x[s], coded ? cnt_s : 0, cur.mu[s], e, K, coded && cur.verify[s], q);
+        bool ok = encode_try<T, EPL>(cur.x[s], coded ? cnt_s : 0, cur.mu[s], e, K, coded && cur.row.verify(s), q);
         if (!group_all<LPB>(ok)) {  // only coded blocks can fail
           const int K1 = kept_bits<T>(K - Traits<T>::KMIN + 1);
           bool ok1 = false;
-          if (K1 != K) ok1 = encode_try<T, EPL>(cur.x[s], cur.cnt[s], cur.mu[s], e, K1, true, q);
+          if (K1 != K) ok1 = encode_try<T, EPL>(cur.x[s], cnt_s, cur.mu[s], e, K1, true, q);
           K = group_all<LPB>(ok1) ? K1 : -1;
         }
         raw = K < 0;
@@ -713,7 +750,7 @@ __device__ __forceinline__ void encode_pass(const CBatch& b, uint32_t* s_scan, u
       uint32_t rtot;
       const uint32_t ex = wg_excl_sum<uint32_t>(lb, s_scan, rtot);
       if (K != 0) {
-        const uint64_t r = cur.r0 + cur.rank[s];
+        const uint64_t r = cur.r0 + cur.row.rank(s);
         const uint64_t k = (uint64_t)t * G::TBLK + (uint64_t)s * G::TB + threadIdx.x / LPB;
         if (lig == 0) {
           out[sec.kbytes + r] = raw ? kRawK : (uint8_t)K;
