@@ -11,7 +11,9 @@
  * These calls block the calling thread until the data is in the file (or in
  * the destination buffer). They allocate their pinned staging on first use
  * and keep it (a process-wide cache, one call at a time holds it); they are
- * not for the allocation-free compression path. Errors set sz_last_error().
+ * not for the allocation-free compression path. The staging's events belong
+ * to the device current at the first call, so `stream` must be a stream of
+ * that device (or the null stream). Errors set sz_last_error().
  */
 #ifndef SZX_IO_H
 #define SZX_IO_H
