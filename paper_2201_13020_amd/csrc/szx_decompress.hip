@@ -148,7 +148,17 @@ __device__ __forceinline__ void store_run(T* __restrict__ y, uint64_t i0, int cn
         u.z = (uint32_t)b;
         u.w = (uint32_t)(b >> 32);
       }
-      p[c] = u;
+      if constexpr (sizeof(T) == 4) {
+        // streamed past the caches: the values are not read again here, and
+        // the field's other passes keep the cache. (Each store of a wave
+        // covers 16 bytes of every 32; float64 lanes, 16 of every 64, ran
+        // four times slower this way and keep ordinary stores.)
+        using v4u = unsigned int __attribute__((ext_vector_type(4)));
+        const v4u nv = {u.x, u.y, u.z, u.w};
+        __builtin_nontemporal_store(nv, reinterpret_cast<v4u*>(p + c));
+      } else {
+        p[c] = u;
+      }
     }
   } else {
 #pragma unroll
