@@ -538,7 +538,28 @@ __device__ __forceinline__ void decode_tile(const FieldD& a, uint32_t t, uint32_
         v[i] = mu[s] + from_bits<T>((U)(qi << sh));
       }
     }
-    if (cnt[s] > 0) store_run<T, EPL>(y_t, (uint32_t)((s * TB + g) * B + lig * EPL), cnt[s], v);
+    if constexpr (sizeof(T) == 8 && SUB == 1) {
+      // float64 tiles of one row: the values pass through the stage in row
+      // order (lane L holds values [L EPL, (L + 1) EPL)), so that every store
+      // of a wave covers 1 KiB without gaps and can stream past the caches
+      __syncthreads();  // every lane is done with the staged mid bytes
+      T* sv = reinterpret_cast<T*>(s_stage);
+#pragma unroll
+      for (int i = 0; i < EPL; ++i) sv[threadIdx.x * EPL + i] = v[i];
+      __syncthreads();
+      using v4u = unsigned int __attribute__((ext_vector_type(4)));
+      for (uint32_t c = threadIdx.x; c < (uint32_t)G::TILE / 2; c += kWG) {
+        const uint32_t i0 = 2 * c;
+        if (i0 + 2 <= nval_t) {
+          const v4u nv = *reinterpret_cast<const v4u*>(sv + i0);
+          __builtin_nontemporal_store(nv, reinterpret_cast<v4u*>(y_t + i0));
+        } else if (i0 < nval_t) {
+          y_t[i0] = sv[i0];
+        }
+      }
+    } else {
+      if (cnt[s] > 0) store_run<T, EPL>(y_t, (uint32_t)((s * TB + g) * B + lig * EPL), cnt[s], v);
+    }
   }
   if (__ballot(bad) != 0 && lane == 0) atomicMax(a.status, kStatusCorrupt);
 }
