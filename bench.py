@@ -32,16 +32,16 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
 BLOCK = 128
-# bench fields: the headline is cfg2; the others are for design measurements
+# bench fields: the headline is turbulence; the others are for design measurements
 FIELDS = {
-    "cfg2": dict(shape=(100, 500, 500), bounds=(1e-2, 1e-3, 1e-4),
+    "turbulence": dict(shape=(100, 500, 500), bounds=(1e-2, 1e-3, 1e-4),
                  desc="100x500x500 float32 turbulence field with 20% zero regions"),
-    "cfg3b": dict(shape=(1 << 28,), bounds=(1e-3, 1e-5),
+    "state": dict(shape=(1 << 28,), bounds=(1e-3, 1e-5),
                   desc="2^28 float64 state vector (exp-decaying complex amplitudes)"),
-    "cfg3a": dict(shape=(1800, 3600), bounds=(1e-3, 1e-5), desc="1800x3600 float32 spherical-harmonic field"),
-    "cfg1": dict(shape=(1 << 20,), bounds=(1e-3,), desc="2^20 float32 sum of sines"),
+    "sphere": dict(shape=(1800, 3600), bounds=(1e-3, 1e-5), desc="1800x3600 float32 spherical-harmonic field"),
+    "sines": dict(shape=(1 << 20,), bounds=(1e-3,), desc="2^20 float32 sum of sines"),
 }
-BOUNDS = FIELDS["cfg2"]["bounds"]
+BOUNDS = FIELDS["turbulence"]["bounds"]
 
 
 def parse():
@@ -55,16 +55,16 @@ def parse():
     ap.add_argument("--profile", action="store_true",
                     help="short eager run for profilers: no CPU baseline, no instrumented pass, plus a plain 256 MiB copy whose HBM counters scale the others")
     ap.add_argument("--io-dir", type=str, default=None, help="io: directory for the stream files (default: a new temporary one)")
-    ap.add_argument("--field", type=str, default="cfg2", choices=sorted(FIELDS) + ["cfg4", "cfg5", "io"],
-                    help="cfg4: the many-field batch (batched launches vs per-field calls); "
-                         "cfg5: the serving loop (continuous batching vs serial FIFO)")
-    ap.add_argument("--batch-fields", type=int, default=4096, help="cfg4: number of fields")
-    ap.add_argument("--tune", action="store_true", help="cfg4: autotune the encode geometry first")
-    ap.add_argument("--cpu-sample-fields", type=int, default=48, help="cfg4: fields the oracle runs on")
-    ap.add_argument("--serve-requests", type=int, default=2000, help="cfg5: requests per load level")
-    ap.add_argument("--serve-slots", type=int, default=4, help="cfg5: streams of the batching server")
-    ap.add_argument("--serve-max-batch", type=int, default=64, help="cfg5: requests per launch group")
-    ap.add_argument("--serve-budget-gib", type=int, default=64, help="cfg5: HBM budget of the server")
+    ap.add_argument("--field", type=str, default="turbulence", choices=sorted(FIELDS) + ["batch", "serve", "io"],
+                    help="batch: the many-field batch (batched launches vs per-field calls); "
+                         "serve: the serving loop (continuous batching vs serial FIFO)")
+    ap.add_argument("--batch-fields", type=int, default=4096, help="batch: number of fields")
+    ap.add_argument("--tune", action="store_true", help="batch: autotune the encode geometry first")
+    ap.add_argument("--cpu-sample-fields", type=int, default=48, help="batch: fields the oracle runs on")
+    ap.add_argument("--serve-requests", type=int, default=2000, help="serve: requests per load level")
+    ap.add_argument("--serve-slots", type=int, default=4, help="serve: streams of the batching server")
+    ap.add_argument("--serve-max-batch", type=int, default=64, help="serve: requests per launch group")
+    ap.add_argument("--serve-budget-gib", type=int, default=64, help="serve: HBM budget of the server")
     return ap.parse_args()
 
 
@@ -99,7 +99,7 @@ def source_hash():
     return h.hexdigest()
 
 
-def recorded_traffic(kernel, tag="cfg2"):
+def recorded_traffic(kernel, tag="turbulence"):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE runs, scaled by a plain copy), or None
     when the summary is missing or the kernels changed since it was taken."""
@@ -130,9 +130,9 @@ def main():
     from paper_2201_13020_amd import synth, szx
 
     assert torch.cuda.is_available(), "bench needs a GPU"
-    if args.field == "cfg4":
+    if args.field == "batch":
         return bench_batch(args)
-    if args.field == "cfg5":
+    if args.field == "serve":
         return bench_serve(args)
     if args.field == "io":
         return bench_io(args)
@@ -583,7 +583,7 @@ def bench_batch(args):
         },
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": kd["achieved_GBps"], "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(kd["achieved_GBps"] / HBM_PEAK_GBPS, 4),
-                     "traffic": recorded_traffic(dom, "cfg4"), "alg_bytes_per_run": kd["alg_bytes_per_run"],
+                     "traffic": recorded_traffic(dom, "batch"), "alg_bytes_per_run": kd["alg_bytes_per_run"],
                      "us_per_run": kd["us_per_run"], "launches_per_run": kd["launches_per_run"]},
     }
     if cpu is not None:
@@ -703,9 +703,9 @@ def bench_io(args):
     import torch
     from paper_2201_13020_amd import synth, szx
 
-    field = FIELDS["cfg2"]
+    field = FIELDS["turbulence"]
     shape = field["shape"]
-    x_np = synth.make("cfg2")
+    x_np = synth.make("turbulence")
     x = torch.from_numpy(x_np).cuda()
     nbytes = x.numel() * x.element_size()
     own_dir = args.io_dir is None

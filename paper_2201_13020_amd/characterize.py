@@ -152,9 +152,9 @@ def _fields(small):
         return {"turbulence 40x100x100": synth.turbulence_3d((40, 100, 100)),
                 "sphere 180x360": synth.sphere_2d(180, 360),
                 "sines 2^18": synth.sines_1d(1 << 18)}
-    return {"turbulence 100x500x500": synth.make("cfg2"),
-            "sphere 1800x3600": synth.make("cfg3a"),
-            "sines 2^20": synth.make("cfg1")}
+    return {"turbulence 100x500x500": synth.make("turbulence"),
+            "sphere 1800x3600": synth.make("sphere"),
+            "sines 2^20": synth.make("sines")}
 
 
 def run(small=False):

@@ -8,15 +8,15 @@ the same shapes and the properties the method depends on: local smoothness
 contain none of the compressor's arithmetic; both the GPU path and the CPU
 oracle consume the same arrays.
 
-Seeds: numpy default_rng(13020 + 1000 * cfg + field). Values are generated in
+Seeds: numpy default_rng(13020 + 1000 * stream + field), one stream per workload. Values are generated in
 float64 and rounded once to the element type. Zeros are assigned (+0.0), never
 produced by multiplying with a mask.
 """
 import numpy as np
 
 
-def _rng(cfg, field=0):
-    return np.random.default_rng(13020 + 1000 * cfg + field)
+def _rng(stream, field=0):
+    return np.random.default_rng(13020 + 1000 * stream + field)
 
 
 def sines_1d(n=1 << 20, field=0, noise=1e-3, dtype=np.float32):
@@ -130,10 +130,10 @@ def qc_state_1d(n=1 << 28, field=0, decay=20.0, chunk=1 << 24):
 
 # The workload configurations. Shapes at full size; tests scale them down.
 CONFIGS = {
-    "cfg1": dict(gen="sines_1d", shape=(1 << 20,), dtype="float32", rel=(1e-3,)),
-    "cfg2": dict(gen="turbulence_3d", shape=(100, 500, 500), dtype="float32", rel=(1e-2, 1e-3, 1e-4)),
-    "cfg3a": dict(gen="sphere_2d", shape=(1800, 3600), dtype="float32", rel=(1e-3, 1e-5)),
-    "cfg3b": dict(gen="qc_state_1d", shape=(1 << 28,), dtype="float64", rel=(1e-3, 1e-5)),
+    "sines": dict(gen="sines_1d", shape=(1 << 20,), dtype="float32", rel=(1e-3,)),
+    "turbulence": dict(gen="turbulence_3d", shape=(100, 500, 500), dtype="float32", rel=(1e-2, 1e-3, 1e-4)),
+    "sphere": dict(gen="sphere_2d", shape=(1800, 3600), dtype="float32", rel=(1e-3, 1e-5)),
+    "state": dict(gen="qc_state_1d", shape=(1 << 28,), dtype="float64", rel=(1e-3, 1e-5)),
 }
 
 
@@ -163,16 +163,16 @@ def make(name, shape=None, field=0):
 # from periodic Gaussian random fields with a k^(-5/3) energy spectrum, half
 # of them with exact-zero regions.
 
-_BATCH_CFG = 6
+_BATCH_STREAM = 6
 
 
 def batch_specs(count=4096, median=1 << 20, sigma=1.25, lo=4 << 10, hi=64 << 20, f64_frac=0.2,
-                ebs=(1e-2, 1e-3, 1e-4), seed_cfg=_BATCH_CFG):
+                ebs=(1e-2, 1e-3, 1e-4), seed_stream=_BATCH_STREAM):
     """Field specs: byte size ~ LogNormal(ln median, sigma) redrawn until it
     lies in [lo, hi]; float64 with probability f64_frac; 1 to 3 dims with
     log-uniform aspect ratios in [1/8, 8] (the element count is the product of
     the dims); a relative bound drawn from ebs."""
-    r = _rng(seed_cfg, 0)
+    r = _rng(seed_stream, 0)
     specs = []
     for i in range(count):
         while True:
@@ -193,7 +193,7 @@ def batch_specs(count=4096, median=1 << 20, sigma=1.25, lo=4 << 10, hi=64 << 20,
         eb = float(ebs[int(r.integers(0, len(ebs)))])
         zero = nd > 1 and r.random() < 0.5
         specs.append(dict(index=i, dims=dims, dtype="float64" if f64 else "float32", eb=eb,
-                          zero_regions=bool(zero), seed=13020 + 1000 * seed_cfg + i))
+                          zero_regions=bool(zero), seed=13020 + 1000 * seed_stream + i))
     return specs
 
 
@@ -239,7 +239,7 @@ def _mothers(device):
     if key not in _MOTHERS:
         big = torch.device(device).type == "cuda"
         g = torch.Generator(device=device)
-        g.manual_seed(13020 + 1000 * _BATCH_CFG + 999_999)
+        g.manual_seed(13020 + 1000 * _BATCH_STREAM + 999_999)
         out = {}
         for nd, shape in ((2, (4096, 4096) if big else (512, 512)), (3, (384, 384, 384) if big else (64, 64, 64))):
             x = _torch_spectral(shape, g, -11.0 / 6.0, device)
@@ -296,7 +296,7 @@ def batch_field(spec, device="cpu"):
 # resident item picked by a uniform draw. numpy default_rng(13020 + 7000 +
 # seed).
 
-_SERVE_CFG = 7
+_SERVE_STREAM = 7
 
 
 def serve_trace(count, rate, seed=0, median=4 << 20, sigma=1.5, lo=64 << 10, hi=256 << 20, f64_frac=0.2,
@@ -304,7 +304,7 @@ def serve_trace(count, rate, seed=0, median=4 << 20, sigma=1.5, lo=64 << 10, hi=
     """Arrays of one trace: t (seconds from the start), kind (0 compress,
     1 decompress), nbytes, f64 (bool), pos (uniform [0, 1): slice offset or
     item pick)."""
-    r = _rng(_SERVE_CFG, seed)
+    r = _rng(_SERVE_STREAM, seed)
     gaps = r.exponential(1.0 / rate, count) if rate > 0 else np.zeros(count)
     t = np.cumsum(gaps) - gaps[0]
     kind = (r.random(count) >= compress_frac).astype(np.int32)

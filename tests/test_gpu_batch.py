@@ -167,7 +167,7 @@ def test_batch_of_4096_fields_full(capsys):
 
     def progress(msg):
         with capsys.disabled():
-            print(f"[cfg4] {msg}", flush=True)
+            print(f"[batch] {msg}", flush=True)
 
     specs = synth.batch_specs(4096)
     r = np.random.default_rng(11)

@@ -110,9 +110,9 @@ def test_parity_ragged_sizes(n):
 
 def test_parity_multidim_metadata():
     from paper_2201_13020_amd import synth
-    x = synth.make("cfg2", (20, 50, 50))
+    x = synth.make("turbulence", (20, 50, 50))
     for eb in [1e-2, 1e-3, 1e-4]:
-        ref = check_parity(x, eb, "rel", 128, "cfg2-small")
+        ref = check_parity(x, eb, "rel", 128, "turbulence-small")
         assert sf.parse(ref)["dims"] == (20, 50, 50)
 
 
@@ -198,24 +198,24 @@ def test_determinism_repeated_calls():
 
 # ------------------------------------------------- full-size workloads --
 
-def test_parity_cfg1_full():
+def test_parity_sines_full():
     from paper_2201_13020_amd import synth
-    x = synth.make("cfg1")
-    check_parity(x, 1e-3, "rel", 128, "cfg1")
+    x = synth.make("sines")
+    check_parity(x, 1e-3, "rel", 128, "sines")
 
 
 @pytest.mark.parametrize("eb", [1e-2, 1e-3, 1e-4])
-def test_parity_cfg2_full(eb):
+def test_parity_turbulence_full(eb):
     from paper_2201_13020_amd import synth
-    x = synth.make("cfg2")
-    check_parity(x, eb, "rel", 128, "cfg2")
+    x = synth.make("turbulence")
+    check_parity(x, eb, "rel", 128, "turbulence")
 
 
 @pytest.mark.parametrize("eb", [1e-3, 1e-5])
-def test_parity_cfg3a_full(eb):
+def test_parity_sphere_full(eb):
     from paper_2201_13020_amd import synth
-    x = synth.make("cfg3a")
-    check_parity(x, eb, "rel", 128, "cfg3a")
+    x = synth.make("sphere")
+    check_parity(x, eb, "rel", 128, "sphere")
 
 
 def test_graph_replays_match_eager():
@@ -270,21 +270,21 @@ def test_graph_replays_match_eager():
         torch.cuda.synchronize()
 
 
-_CFG3B = {}
+_STATE = {}
 
 
-def _cfg3b():
-    if "x" not in _CFG3B:
+def _state():
+    if "x" not in _STATE:
         from paper_2201_13020_amd import synth
-        _CFG3B["x"] = synth.make("cfg3b")
-    return _CFG3B["x"]
+        _STATE["x"] = synth.make("state")
+    return _STATE["x"]
 
 
 @pytest.mark.parametrize("eb", [1e-3, 1e-5])
-def test_parity_cfg3b_full(eb):
+def test_parity_state_full(eb):
     """2^28 float64 values (2 GiB): byte-exact stream and bit-exact values."""
-    x = _cfg3b()
-    ref = check_parity(x, eb, "rel", 128, "cfg3b")
+    x = _state()
+    ref = check_parity(x, eb, "rel", 128, "state")
     info = sf.parse(ref)
-    print(f"[cfg3b] eb={eb} CR={x.nbytes / ref.size:.3f} constant blocks "
+    print(f"[state] eb={eb} CR={x.nbytes / ref.size:.3f} constant blocks "
           f"{1 - info['n_nc'] / info['nblk']:.3f}", flush=True)

@@ -21,7 +21,7 @@ def _need_gpu():
 
 def _fields(count, seed):
     from paper_2201_13020_amd import synth
-    specs = synth.batch_specs(count, median=256 << 10, hi=8 << 20, seed_cfg=60 + seed)
+    specs = synth.batch_specs(count, median=256 << 10, hi=8 << 20, seed_stream=60 + seed)
     return specs, [synth.batch_field(sp, "cuda") for sp in specs]
 
 
