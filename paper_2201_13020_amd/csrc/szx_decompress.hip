@@ -216,11 +216,27 @@ __device__ __forceinline__ uint32_t block_mid_bytes(const uint8_t* cp, uint32_t 
   // B/4 code bytes, 4 codes per byte, first value in the top bits; read in
   // aligned words of 16 codes (b = 8 has one half word)
   constexpr uint32_t NW = B >= 16 ? B / 16 : 1;
+  // a block's codes start 16-byte aligned (the codes section is, and each
+  // block holds b / 4 bytes), so from b = 64 on they load as 16-byte words
+  uint32_t raw[NW];
+  if constexpr (B >= 64) {
+#pragma unroll
+    for (uint32_t q = 0; q < NW / 4; ++q) {
+      const uint4 u = reinterpret_cast<const uint4*>(cp)[q];
+      raw[4 * q + 0] = u.x;
+      raw[4 * q + 1] = u.y;
+      raw[4 * q + 2] = u.z;
+      raw[4 * q + 3] = u.w;
+    }
+  } else if constexpr (B >= 16) {
+#pragma unroll
+    for (uint32_t j = 0; j < NW; ++j) raw[j] = reinterpret_cast<const uint32_t*>(cp)[j];
+  }
 #pragma unroll
   for (uint32_t j = 0; j < NW; ++j) {
     uint32_t w;
     if constexpr (B >= 16) {
-      w = __builtin_bswap32(reinterpret_cast<const uint32_t*>(cp)[j]);
+      w = __builtin_bswap32(raw[j]);
     } else {
       const uint32_t h2 = *reinterpret_cast<const uint16_t*>(cp);
       w = ((h2 & 0xFFu) << 24) | ((h2 >> 8) << 16);
