@@ -346,12 +346,28 @@ __device__ __forceinline__ void classify_tile(const FieldC& f, uint32_t t, uint3
   const U* stats = reinterpret_cast<const U*>(f.stats);
   const uint64_t nblk = f.nblk;
   const uint64_t k0 = (uint64_t)t * CLS + (uint64_t)threadIdx.x * BPT;
+  static_assert(BPT == 4, "four blocks per thread");
+  // a thread's blocks are consecutive and start 16-byte aligned in the
+  // extrema, mu and plan arrays, so a full group moves as 16-byte words
+  const bool full = k0 + BPT <= nblk;
   U kmin[BPT], kmax[BPT];
+  if (full) {
+    U w[2 * BPT];
+    constexpr int NQ = 2 * BPT * (int)sizeof(U) / 16;
 #pragma unroll
-  for (int i = 0; i < BPT; ++i) {
-    const uint64_t k = k0 + i;
-    kmin[i] = k < nblk ? stats[2 * k] : (U)0;
-    kmax[i] = k < nblk ? stats[2 * k + 1] : (U)0;
+    for (int q = 0; q < NQ; ++q) reinterpret_cast<uint4*>(w)[q] = reinterpret_cast<const uint4*>(stats + 2 * k0)[q];
+#pragma unroll
+    for (int i = 0; i < BPT; ++i) {
+      kmin[i] = w[2 * i];
+      kmax[i] = w[2 * i + 1];
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < BPT; ++i) {
+      const uint64_t k = k0 + i;
+      kmin[i] = k < nblk ? stats[2 * k] : (U)0;
+      kmax[i] = k < nblk ? stats[2 * k + 1] : (U)0;
+    }
   }
   const uint64_t e_bits = bound_bits(f);
   const T e = from_bits<T>((U)e_bits);
@@ -361,16 +377,33 @@ __device__ __forceinline__ void classify_tile(const FieldC& f, uint32_t t, uint3
   for (int i = threadIdx.x; i < CLS / 32; i += kWG) s_state[i] = 0;
   __syncthreads();
   uint32_t cnt = 0, bits = 0;
+  T mv[BPT];
+  uint32_t pv = 0;  // plan bytes, block i in byte i
 #pragma unroll
   for (int i = 0; i < BPT; ++i) {
     const uint64_t k = k0 + i;
+    mv[i] = (T)0;
     if (k < nblk) {
       const BlockPlan<T> p = plan_block<T>(kmin[i], kmax[i], e);
-      mus[k] = p.mu;
-      f.plan[k] = (uint8_t)plan_byte(p);
+      mv[i] = p.mu;
+      pv |= plan_byte(p) << (8 * i);
       const bool nc = p.K != 0;
       cnt += nc ? 1u : 0u;
       bits |= (nc ? 1u : 0u) << i;
+    }
+  }
+  if (full) {
+    constexpr int NQ = BPT * (int)sizeof(T) / 16;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) reinterpret_cast<uint4*>(mus + k0)[q] = reinterpret_cast<const uint4*>(mv)[q];
+    *reinterpret_cast<uint32_t*>(f.plan + k0) = pv;
+  } else {
+#pragma unroll
+    for (int i = 0; i < BPT; ++i) {
+      if (k0 + i < nblk) {
+        mus[k0 + i] = mv[i];
+        f.plan[k0 + i] = (uint8_t)(pv >> (8 * i));
+      }
     }
   }
   if (bits) atomicOr(&s_state[(threadIdx.x * BPT) / 32], bits << ((threadIdx.x * BPT) % 32));
