@@ -185,8 +185,12 @@ __device__ __forceinline__ void stats_tile(const T (&v)[Geo<T, B>::EPL], int cnt
   const uint64_t blk = i0 / B;
   const bool last = (threadIdx.x % LPB) == LPB - 1;
   if (last && blk < nblk) {
-    stats[2 * blk] = kmin;
-    stats[2 * blk + 1] = kmax;
+    // one store for the pair (8- or 16-byte aligned: the array starts 256-byte aligned)
+    if constexpr (sizeof(U) == 4) {
+      *reinterpret_cast<uint2*>(stats + 2 * blk) = make_uint2(kmin, kmax);
+    } else {
+      *reinterpret_cast<ulonglong2*>(stats + 2 * blk) = make_ulonglong2(kmin, kmax);
+    }
   }
   // finite range: a block whose extrema are finite is finite throughout and
   // adds [kmin, kmax]; a block holding a NaN or an infinity (rare) adds its
@@ -864,7 +868,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Geo<T, B>::
 __global__ void k_finalize(CBatch b) {
   const FieldC f = field_at(b, blockIdx.x);
   const Counters* ctr = f.ctr;
-  const uint64_t e_bits = bound_bits(f);
+  // classification stores the bound (its first tile); a field without
+  // blocks has no classification tile and folds the range itself
+  const uint64_t e_bits = f.nblk ? ctr->e_bits : bound_bits(f);
   const uint32_t w = f.dtype == 0 ? 4 : 8;
   const uint64_t n_nc = ctr->n_nc, mid_total = ctr->mid_total;
   const Sections s = sections(f.nblk, n_nc, w, f.b, mid_total);
