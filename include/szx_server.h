@@ -64,11 +64,15 @@ typedef struct {
   uint64_t t_done;        /* group's work finished on the device (observed on the host) */
   uint32_t group_size;    /* requests in its launch group */
   uint32_t slot;
+  uint64_t t_dev_begin;   /* its group's span on the device: HIP events on the slot's
+                             stream before the group's first copy and after its last, */
+  uint64_t t_dev_end;     /* in ns from an event recorded at creation (0: unavailable) */
 } sz_completion;
 
 typedef struct {
   uint64_t arena_bytes, arena_in_use, arena_peak;
   uint64_t queued, in_flight_groups, groups_launched, completed, items_resident;
+  uint64_t peak_in_flight_groups; /* most launch groups launched and not yet completed at once */
 } sz_server_stats;
 
 /* Create a server on cfg->device (allocates the arena, streams with default

@@ -71,7 +71,8 @@ struct Group {
 
 struct Slot {
   hipStream_t stream = nullptr;
-  hipEvent_t done = nullptr;
+  hipEvent_t begin = nullptr;  // recorded before the group's first copy
+  hipEvent_t done = nullptr;   // after its last copy
   std::thread th;
   std::condition_variable cv;
   std::unique_ptr<Group> g;  // in flight
@@ -95,8 +96,9 @@ struct sz_server_s {
   std::deque<sz_completion> done_q;
   std::unordered_map<uint64_t, Item> items;
   uint64_t next_req = 1, next_item = 1;
-  uint64_t in_flight = 0, groups = 0, completed = 0;
+  uint64_t in_flight = 0, peak_in_flight = 0, groups = 0, completed = 0;
   bool stop = false, stop_all = false;
+  hipEvent_t ref = nullptr;  // device time origin of the groups' begin/end stamps
   std::chrono::steady_clock::time_point t0;
 
   uint64_t now() const {
@@ -252,8 +254,8 @@ void launch_group(sz_server_s* S, uint32_t k, std::unique_ptr<Group> g, const Gr
     fail_group(S, *g, s);
     return;
   }
-  hipError_t e = hipSuccess;
-  if (!img_c.empty()) {
+  hipError_t e = hipEventRecord(sl.begin, sl.stream);
+  if (e == hipSuccess && !img_c.empty()) {
     memcpy(sl.stage, img_c.data(), img_c.size());
     e = hipMemcpyAsync(S->base + g->ws_off, sl.stage, img_c.size(), hipMemcpyHostToDevice, sl.stream);
   }
@@ -277,6 +279,7 @@ void launch_group(sz_server_s* S, uint32_t k, std::unique_ptr<Group> g, const Gr
     return;
   }
   ++S->in_flight;
+  S->peak_in_flight = std::max(S->peak_in_flight, S->in_flight);
   ++S->groups;
   sl.g = std::move(g);
   sl.cv.notify_one();
@@ -351,6 +354,10 @@ void completion_main(sz_server_s* S, uint32_t k) {
     lk.unlock();
     const hipError_t e = hipEventSynchronize(sl.done);
     const uint64_t t_done = S->now();
+    // the group's span on the device, from the two events on its stream
+    float ms_b = 0.f, ms_e = 0.f;
+    const bool stamped = e == hipSuccess && hipEventElapsedTime(&ms_b, S->ref, sl.begin) == hipSuccess &&
+                         hipEventElapsedTime(&ms_e, S->ref, sl.done) == hipSuccess;
     lk.lock();
     Group& g = *sl.g;
     const uint64_t* sizes = (const uint64_t*)sl.results;
@@ -401,6 +408,8 @@ void completion_main(sz_server_s* S, uint32_t k) {
       c.status = st;
       c.t_admit = g.t_admit;
       c.t_done = t_done;
+      c.t_dev_begin = stamped ? (uint64_t)((double)ms_b * 1e6) : 0;
+      c.t_dev_end = stamped ? (uint64_t)((double)ms_e * 1e6) : 0;
       c.group_size = n;
       c.slot = k;
       S->done_q.push_back(c);
@@ -439,12 +448,15 @@ sz_status sz_server_create(const sz_server_config* cfg, sz_server* out) {
   for (uint32_t k = 0; k < cfg->slots && ok; ++k) {
     auto sl = std::make_unique<Slot>();
     ok = hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking) == hipSuccess &&
-         hipEventCreateWithFlags(&sl->done, hipEventDisableTiming) == hipSuccess &&
+         hipEventCreate(&sl->begin) == hipSuccess && hipEventCreate(&sl->done) == hipSuccess &&
          hipHostMalloc((void**)&sl->results, kResultBytes * cfg->max_batch + 256, hipHostMallocDefault) ==
              hipSuccess &&
          grow_stage(*sl, 1 << 20);
     S->slots.push_back(std::move(sl));
   }
+  // the device time origin of the groups' stamps
+  ok = ok && hipEventCreate(&S->ref) == hipSuccess && hipEventRecord(S->ref, S->slots[0]->stream) == hipSuccess &&
+       hipEventSynchronize(S->ref) == hipSuccess;
   sz_server_s* raw = S.release();
   if (!ok) {
     sz_server_destroy(raw);
@@ -477,10 +489,12 @@ void sz_server_destroy(sz_server S) {
   (void)hipSetDevice(S->cfg.device);
   for (auto& sl : S->slots) {
     if (sl->stream) (void)hipStreamDestroy(sl->stream);
+    if (sl->begin) (void)hipEventDestroy(sl->begin);
     if (sl->done) (void)hipEventDestroy(sl->done);
     if (sl->stage) (void)hipHostFree(sl->stage);
     if (sl->results) (void)hipHostFree(sl->results);
   }
+  if (S->ref) (void)hipEventDestroy(S->ref);
   if (S->base) (void)hipFree(S->base);
   delete S;
 }
@@ -599,6 +613,7 @@ sz_status sz_server_get_stats(sz_server S, sz_server_stats* out) {
   out->arena_peak = S->arena.peak();
   out->queued = S->queue.size();
   out->in_flight_groups = S->in_flight;
+  out->peak_in_flight_groups = S->peak_in_flight;
   out->groups_launched = S->groups;
   out->completed = S->completed;
   out->items_resident = S->items.size();

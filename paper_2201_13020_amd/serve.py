@@ -25,7 +25,8 @@ class SzCompletion(ctypes.Structure):
     _fields_ = [("request", ctypes.c_uint64), ("kind", ctypes.c_uint32), ("status", ctypes.c_uint32),
                 ("item", ctypes.c_uint64), ("out_item", ctypes.c_uint64), ("bytes_in", ctypes.c_uint64),
                 ("stream_bytes", ctypes.c_uint64), ("t_arrival", ctypes.c_uint64), ("t_admit", ctypes.c_uint64),
-                ("t_done", ctypes.c_uint64), ("group_size", ctypes.c_uint32), ("slot", ctypes.c_uint32)]
+                ("t_done", ctypes.c_uint64), ("group_size", ctypes.c_uint32), ("slot", ctypes.c_uint32),
+                ("t_dev_begin", ctypes.c_uint64), ("t_dev_end", ctypes.c_uint64)]
 
 
 class SzTraceReq(ctypes.Structure):
@@ -36,7 +37,7 @@ class SzTraceReq(ctypes.Structure):
 class SzServerStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in ("arena_bytes", "arena_in_use", "arena_peak", "queued",
                                                "in_flight_groups", "groups_launched", "completed",
-                                               "items_resident")]
+                                               "items_resident", "peak_in_flight_groups")]
 
 
 _bound = False

@@ -184,12 +184,16 @@ def compress(x, eb, mode="rel", block=128, dims=None, out=None, out_size=None, w
     wsz = int(lib().sz_workspace_size(ctypes.byref(p)))
     if cap == 0 or wsz == 0:
         raise SzError(1, "invalid parameters: " + lib().sz_last_error().decode())
-    if out is None:
-        out = torch.empty(cap, dtype=torch.uint8, device=x.device)
-    if out_size is None:
-        out_size = torch.empty(1, dtype=torch.uint64, device=x.device)
-    if ws is None:
-        ws = torch.empty(wsz, dtype=torch.uint8, device=x.device)
+    # buffers made here belong to the stream the kernels run on, so that the
+    # caching allocator does not hand them out again while that stream still
+    # uses them
+    with torch.cuda.stream(stream if stream is not None else torch.cuda.current_stream(x.device)):
+        if out is None:
+            out = torch.empty(cap, dtype=torch.uint8, device=x.device)
+        if out_size is None:
+            out_size = torch.empty(1, dtype=torch.uint64, device=x.device)
+        if ws is None:
+            ws = torch.empty(wsz, dtype=torch.uint8, device=x.device)
     rc = lib().sz_compress(ctypes.byref(p), _ptr(x), _ptr(out), out.numel(), _ptr(out_size),
                            _ptr(ws), ws.numel(), _stream_handle(stream))
     _check(rc, "sz_compress")
@@ -227,12 +231,13 @@ def decompress(data, nbytes, expected, out=None, status=None, ws=None, stream=No
     n = 1
     for d in expected["dims"]:
         n *= int(d)
-    if out is None:
-        out = torch.empty(n, dtype=dt, device=data.device)
-    if status is None:
-        status = torch.empty(1, dtype=torch.uint32, device=data.device)
-    if ws is None:
-        ws = torch.empty(wsz, dtype=torch.uint8, device=data.device)
+    with torch.cuda.stream(stream if stream is not None else torch.cuda.current_stream(data.device)):
+        if out is None:
+            out = torch.empty(n, dtype=dt, device=data.device)
+        if status is None:
+            status = torch.empty(1, dtype=torch.uint32, device=data.device)
+        if ws is None:
+            ws = torch.empty(wsz, dtype=torch.uint8, device=data.device)
     rc = lib().sz_decompress(_ptr(data), int(nbytes), ctypes.byref(p), _ptr(out), out.numel() * out.element_size(),
                              _ptr(status), _ptr(ws), ws.numel(), _stream_handle(stream))
     _check(rc, "sz_decompress")

@@ -116,16 +116,22 @@ def test_parity_multidim_metadata():
         assert sf.parse(ref)["dims"] == (20, 50, 50)
 
 
-def test_parity_ladder_and_raw_escalation():
-    """Blocks whose bound has a mantissa near 2 and mid values far from the
-    data make the first bit budget fail; the escalation must match."""
-    r = np.random.default_rng(6)
-    x = (1e6 + r.standard_normal(64 * 2000) * 1e3).astype(np.float32)
-    e = np.float32(1.9999) * np.float32(2.0 ** -3)
-    ref = check_parity(x, float(e), "abs", 64, "ladder")
-    info = sf.parse(ref)
-    ks = info["K"]
-    assert len(set(ks.tolist())) >= 2
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("block", [8, 128])
+def test_parity_ladder_and_raw_escalation(dtype, block):
+    """The error-control ladder: with a subnormal absolute bound the first
+    rung (K0 kept bits) can fail. The oracle's stream for this field holds
+    blocks kept at K0, blocks kept at K0 + 1 and finite blocks stored raw
+    with K0 < W (outcomes from the definitions, tests/ladder.py); the GPU
+    stream must equal it byte for byte."""
+    import ladder
+    x, eb = ladder.subnormal_field(dtype, 400, block, 7)
+    ref = check_parity(x, eb, "abs", block, "ladder")
+    got = ladder.outcomes_of_stream(x, sf.parse(ref))
+    W = ladder.spec(dtype)[0]
+    assert sum(1 for o, K0 in got if o == "K0+1") >= 40
+    assert sum(1 for o, K0 in got if o == "raw" and K0 < W) >= 40
+    assert sum(1 for o, K0 in got if o == "K0") >= 40
 
 
 def test_golden_index_propagation_stream():
@@ -186,6 +192,32 @@ def test_decoder_flags_codes_above_kept_bytes(dtype):
         assert st == 3, (r, span)
     y, st = gpu_decompress(ref, exp)
     assert st == 0 and same_bits(y, szref.decompress(ref))
+
+
+def test_side_stream_while_current_stream_allocates():
+    """Calls on a side stream while torch's current stream allocates and
+    writes memory: the buffers the binding makes belong to the side stream,
+    so nothing it still uses is handed out again. Results equal the oracle."""
+    from paper_2201_13020_amd import szx
+    x_np = smooth(2_000_003, 11)
+    x = torch.from_numpy(x_np).cuda()
+    ref = szref.compress(x_np, 1e-3, "rel", 128)
+    yref = szref.decompress(ref)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    exp = dict(dtype=torch.float32, dims=tuple(x.shape), block=128)
+    for rep in range(3):
+        out, size = szx.compress(x, 1e-3, "rel", 128, stream=s)
+        churn = [torch.full((1 << 20,), rep + 1, dtype=torch.uint8, device="cuda") for _ in range(32)]
+        del churn
+        y, st = szx.decompress(out, out.numel(), exp, stream=s)
+        churn = [torch.full((1 << 20,), 0xFF, dtype=torch.uint8, device="cuda") for _ in range(32)]
+        del churn
+        s.synchronize()
+        n = int(size.cpu().view(torch.int64).item())
+        assert np.array_equal(out[:n].cpu().numpy(), ref), f"rep {rep}"
+        assert int(st.cpu().view(torch.int32).item()) == 0
+        assert same_bits(y.cpu().numpy(), yref), f"rep {rep}"
 
 
 def test_determinism_repeated_calls():

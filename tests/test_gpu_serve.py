@@ -74,6 +74,14 @@ def test_results_identical_alone_and_in_mix():
         comps = _drain(srv, len(req2))
         groups = [c["group_size"] for c in comps]
         assert max(groups) > 1, "requests were never grouped"
+        # continuous batching overlaps on the device: two launch groups on
+        # different slots whose spans (events on their streams) intersect
+        spans = {(c["slot"], c["t_dev_begin"], c["t_dev_end"]) for c in comps}
+        assert all(e > b > 0 for _, b, e in spans), spans
+        spans = sorted(spans, key=lambda t: t[1])
+        overlap = any(s2[0] != s1[0] and s2[1] < s1[2] for i, s1 in enumerate(spans) for s2 in spans[i + 1:])
+        assert overlap, f"no two launch groups overlapped on the device: {spans}"
+        assert srv.stats()["peak_in_flight_groups"] >= 2
         for c in comps:
             kind, i = req2[c["request"]]
             assert c["status"] == 0, (kind, i)

@@ -298,6 +298,59 @@ def test_p4_bit_budget_brute_force():
     assert adversarial_checked > 50
 
 
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_p4_ladder_second_rung_and_raw(dtype):
+    """The error-control ladder (error control of Sec. I; Alg. 1's bit
+    budget): with a subnormal bound e, 2^p(e) exceeds e, so the first rung
+    (K0 kept bits, eq. (4)) can fail; the oracle must then store the block at
+    K0 + 1 when that passes, else raw. Outcomes decided by brute force with
+    rationals (ladder.py), on hand-made and seeded blocks."""
+    import ladder
+    W = ladder.spec(dtype)[0]
+    for blk, eb, want in ladder.constructed_blocks(dtype):
+        s = szref.compress(blk, eb, "abs", 8)
+        info = sf.parse(s)
+        assert info["state"][0]
+        got, K0 = ladder.expected_outcome(blk, info["e"])
+        assert got == want and K0 < W
+        assert ladder.outcomes_of_stream(blk, info) == [(want, K0)]
+        assert within(blk, szref.decompress(s), info["e"])
+    seen = {"K0": 0, "K0+1": 0, "raw": 0}
+    blocks, bounds = ladder.subnormal_blocks(dtype, 240, 31)
+    for blk, e in zip(blocks, bounds):
+        s = szref.compress(blk, float(e), "abs", 8)
+        info = sf.parse(s)
+        assert info["e"] == e
+        if not info["state"][0]:
+            continue
+        want, K0 = ladder.expected_outcome(blk, e)
+        assert ladder.outcomes_of_stream(blk, info) == [(want, K0)], (blk, e)
+        seen[want] += 1
+        assert within(blk, szref.decompress(s), e)
+    assert min(seen.values()) >= 5, seen
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("block", [8, 128])
+def test_p4_ladder_field_outcomes(dtype, block):
+    """The field the GPU ladder test uses: every non-constant block's stored
+    outcome (K0, K0 + 1 or raw) equals the brute-force outcome, and each
+    outcome occurs many times."""
+    import ladder
+    x, eb = ladder.subnormal_field(dtype, 400, block, 7)
+    s = szref.compress(x, eb, "abs", block)
+    info = sf.parse(s)
+    got = ladder.outcomes_of_stream(x, info)
+    ks = np.nonzero(info["state"])[0]
+    assert len(got) == len(ks)
+    for k, (o, K0) in zip(ks, got):
+        want, K0w = ladder.expected_outcome(np.ascontiguousarray(x[k * block:(k + 1) * block]), info["e"])
+        assert (o, K0) == (want, K0w), k
+    counts = {o: sum(1 for g, _ in got if g == o) for o in ("K0", "K0+1", "raw")}
+    assert min(counts.values()) >= 40, counts
+    assert within(x, szref.decompress(s), info["e"])
+
+
 def test_p4_truncation_bound_exhaustive_window():
     """For every float32 |v| <= r in a window of binades, keeping m0 mantissa
     bits errs by < 2^(p(r) - m0) (the bound eq. (4) relies on)."""
