@@ -110,6 +110,27 @@ sz_status sz_decompress(const void* d_in, uint64_t in_bytes,
                         uint32_t* d_status, void* d_ws, uint64_t ws_bytes,
                         hipStream_t stream);
 
+/* ---- allocation-free compression ------------------------------------------
+   For callers that cannot allocate device memory at all (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc) and cannot
+   provide a workspace either. Same arguments, kernels and output bytes as
+   sz_compress, without d_ws: the workspace is a static device array of
+   SZ_NOALLOC_SCRATCH_BYTES bytes inside the library, one per GPU, held from
+   the library's load on that device until the process ends. Its device
+   address is looked up on the first call on each device (with that device
+   current); no call allocates or frees device memory.
+   Limit: fields whose sz_workspace_size exceeds SZ_NOALLOC_SCRATCH_BYTES are
+   rejected with SZ_EUNSUPPORTED before any device call (at b = 128 that is
+   above about 1.75 GB of float32 or 1.85 GB of float64 values).
+   Every call on one GPU shares that GPU's array: calls that overlap on the
+   same GPU (on different streams, or from different threads) race and
+   corrupt each other's output; serialise them, e.g. on one stream. The
+   kernels clear what must start at zero at the start of every call. */
+#define SZ_NOALLOC_SCRATCH_BYTES (32ull << 20)
+sz_status sz_compress_noalloc(const sz_params* p, const void* d_in, void* d_out,
+                              uint64_t out_cap, uint64_t* d_out_size,
+                              hipStream_t stream);
+
 /* ---- batches (many fields, one launch per pass) ---------------------------
    A batch compresses (or decompresses) many fields of mixed element types,
    sizes and bounds with one launch per pass over all of them: one extrema

@@ -473,6 +473,62 @@ sz_status sz_compress(const sz_params* p, const void* d_in, void* d_out, uint64_
   return SZ_OK;
 }
 
+}  // extern "C"
+
+// ---- allocation-free compression ------------------------------------------
+// The workspace of sz_compress_noalloc: one array per GPU, held from the
+// library's load on that device until the process ends. Host code never uses
+// this name as an address: its device address comes from hipGetSymbolAddress,
+// once per device, and is kept in g_scratch_ptr.
+static __device__ __align__(256) uint8_t scratch[SZ_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];  // device address of `scratch` per device (null: not yet looked up)
+
+// Device address of the current device's scratch array, looked up on the
+// first call on that device. Returns SZ_OK and sets *out, or an error.
+sz_status scratch_of_current_device(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(SZ_EDEVICE, std::string("hipGetDevice failed: ") + hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return fail(SZ_EUNSUPPORTED, "device ordinal beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(SZ_EDEVICE, std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return SZ_OK;
+}
+}  // namespace
+
+extern "C" {
+
+sz_status sz_compress_noalloc(const sz_params* p, const void* d_in, void* d_out, uint64_t out_cap,
+                              uint64_t* d_out_size, hipStream_t stream) {
+  g_err.clear();
+  szx::Job j;
+  sz_status s = make_job(p, j);
+  if (s != SZ_OK) return s;
+  // the size limit is decided on the host, before any device call
+  const uint64_t need = szx::ws_layout(j.n, j.nblk, j.w, j.b).total;
+  if (need > SZ_NOALLOC_SCRATCH_BYTES)
+    return fail(SZ_EUNSUPPORTED, "field needs " + std::to_string(need) +
+                                     " bytes of scratch, above the " + std::to_string(SZ_NOALLOC_SCRATCH_BYTES) +
+                                     " bytes of sz_compress_noalloc (use sz_compress with a workspace)");
+  void* ptr = nullptr;
+  s = scratch_of_current_device(&ptr);
+  if (s != SZ_OK) return s;
+  // the same kernels as sz_compress; they clear the workspace words that must
+  // start at zero (counters, range slots, tickets, scan status words) first
+  return sz_compress(p, d_in, d_out, out_cap, d_out_size, ptr, SZ_NOALLOC_SCRATCH_BYTES, stream);
+}
+
 sz_status sz_decompress(const void* d_in, uint64_t in_bytes, const sz_params* expected, void* d_out,
                         uint64_t out_cap, uint32_t* d_status, void* d_ws, uint64_t ws_bytes,
                         hipStream_t stream) {

@@ -64,6 +64,8 @@ def lib():
         L.sz_workspace_size.restype = u64
         L.sz_compress.argtypes = [P, vp, vp, u64, vp, vp, u64, vp]
         L.sz_compress.restype = ctypes.c_int
+        L.sz_compress_noalloc.argtypes = [P, vp, vp, u64, vp, vp]
+        L.sz_compress_noalloc.restype = ctypes.c_int
         L.sz_decompress.argtypes = [vp, u64, P, vp, u64, vp, vp, u64, vp]
         L.sz_decompress.restype = ctypes.c_int
         L.sz_inspect.argtypes = [vp, u64, P, ctypes.POINTER(u64)]
@@ -197,6 +199,30 @@ def compress(x, eb, mode="rel", block=128, dims=None, out=None, out_size=None, w
     rc = lib().sz_compress(ctypes.byref(p), _ptr(x), _ptr(out), out.numel(), _ptr(out_size),
                            _ptr(ws), ws.numel(), _stream_handle(stream))
     _check(rc, "sz_compress")
+    return out, out_size
+
+
+def compress_noalloc(x, eb, mode="rel", block=128, dims=None, out=None, out_size=None, stream=None):
+    """sz_compress_noalloc: as compress(), with the library's static device
+    scratch array as the workspace (no workspace tensor). Calls on one GPU
+    share that array and must not overlap."""
+    if not (x.is_cuda and x.is_contiguous() and x.dtype in (torch.float32, torch.float64)):
+        raise ValueError("x must be a contiguous float32/float64 device tensor")
+    dims = tuple(x.shape) if dims is None else tuple(dims)
+    if len(dims) == 0:
+        dims = (1,)
+    p = make_params(x.dtype, dims, eb, mode, block)
+    cap = int(lib().sz_compress_bound(ctypes.byref(p)))
+    if cap == 0:
+        raise SzError(1, "invalid parameters: " + lib().sz_last_error().decode())
+    with torch.cuda.stream(stream if stream is not None else torch.cuda.current_stream(x.device)):
+        if out is None:
+            out = torch.empty(cap, dtype=torch.uint8, device=x.device)
+        if out_size is None:
+            out_size = torch.empty(1, dtype=torch.uint64, device=x.device)
+    rc = lib().sz_compress_noalloc(ctypes.byref(p), _ptr(x), _ptr(out), out.numel(), _ptr(out_size),
+                                   _stream_handle(stream))
+    _check(rc, "sz_compress_noalloc")
     return out, out_size
 
 

@@ -131,3 +131,18 @@ def test_server_entry_points_fail_cleanly_without_a_device():
     cfg = serve.SzServerConfig(device=0, hbm_budget=1 << 30, slots=0, max_batch=1, block_size=128)
     h = ctypes.c_void_p()
     assert L.sz_server_create(ctypes.byref(cfg), ctypes.byref(h)) == 1  # slots out of range
+
+
+def test_noalloc_size_limit_is_decided_on_the_host():
+    """sz_compress_noalloc rejects a field whose workspace exceeds its static
+    scratch array before any device call (so this runs without a GPU)."""
+    import torch
+    from paper_2201_13020_amd import szx
+    L = szx.lib()
+    dims = (1 << 31,)
+    assert szx.workspace_size(torch.float32, dims, 1e-3, "rel", 128) > (32 << 20)
+    p = szx.make_params("float32", dims, 1e-3, "rel", 128)
+    assert L.sz_compress_noalloc(ctypes.byref(p), None, None, 0, None, None) == 6  # SZ_EUNSUPPORTED
+    assert b"scratch" in L.sz_last_error()
+    p.block_size = 12
+    assert L.sz_compress_noalloc(ctypes.byref(p), None, None, 0, None, None) == 1  # SZ_EINVAL
