@@ -15,11 +15,17 @@ them directly instead.
 
 Prints one JSON line. `value` is the round-trip throughput in GB/s of
 uncompressed bytes: bytes compressed in the step divided by the time of the
-step (compress + decompress). Per-bound compress/decompress GB/s, ratios and
-HBM fractions are in `detail`. `roofline` is the dominant kernel's
-algorithmic bytes per launch over its average launch duration (HIP events on
-its stream during a second, instrumented timed region). `cpu_baseline` is the
-CPU oracle (single thread) on the same field and bounds.
+step (compress + decompress). `detail.per_bound` holds, per bound, compress
+and decompress GB/s, their fractions of the HBM peak by uncompressed and by
+algorithmic bytes, the ratio, max error and PSNR (eq. (7)), block fractions,
+K and code histograms and the error-control ladder's outcomes;
+`detail.kernels` the per-kernel durations. The default run also measures the
+2^28 float64 state vector the same way (`detail.state_2p28_float64`).
+`roofline` is the dominant kernel's algorithmic bytes per launch over its
+average launch duration (HIP events on its stream during a second,
+instrumented timed region). `cpu_baseline` is the CPU oracle on the same
+field and bounds: all cores of the affinity mask at once (one process per
+core on disjoint block ranges), with the single-thread figure beside it.
 """
 import argparse
 import json
@@ -52,6 +58,7 @@ def parse():
     ap.add_argument("--copies", type=int, default=4)
     ap.add_argument("--eager", action="store_true", help="launch directly instead of graph replay")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-state", action="store_true", help="skip the 2^28 float64 field of the default run")
     ap.add_argument("--profile", action="store_true",
                     help="short eager run for profilers: no CPU baseline, no instrumented pass, plus a plain 256 MiB copy whose HBM counters scale the others")
     ap.add_argument("--io-dir", type=str, default=None, help="io: directory for the stream files (default: a new temporary one)")
@@ -120,28 +127,197 @@ def recorded_traffic(kernel, tag="turbulence"):
     return None
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1 (sharding over several GPUs is a design, not built)"}))
-        sys.exit(2)
+def cpu_model():
+    """The host CPU's model name from /proc/cpuinfo ("unknown" if absent)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.lower().startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_cores():
+    """CPUs this process may run on (its affinity mask), at most 16: the
+    share of the host that one GPU's job may use."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def _oracle_worker(task):
+    """One CPU worker of the all-cores leg: compress + decompress its slice of
+    the field at every bound with the oracle until `seconds` have passed.
+    Returns (bytes processed, compress s, decompress s)."""
+    x, bounds, block, seconds, cpu = task
+    if cpu is not None:
+        try:
+            os.sched_setaffinity(0, {cpu})
+        except (AttributeError, OSError):
+            pass
+    sys.path.insert(0, ROOT)
+    from oracle import szref
+    tc = td = 0.0
+    done = 0
+    while done == 0 or tc + td < seconds:
+        for eb in bounds:
+            t0 = time.perf_counter()
+            ref = szref.compress(x, eb, "rel", block)
+            t1 = time.perf_counter()
+            szref.decompress(ref)
+            t2 = time.perf_counter()
+            tc += t1 - t0
+            td += t2 - t1
+            done += x.nbytes
+    return done, tc, td
+
+
+def cpu_all_cores(x_np, bounds, seconds=8.0):
+    """The oracle on P disjoint block-range slices of the field at once, one
+    process per core of the affinity mask (a timing context: each slice takes
+    its own relative bound and the streams are not joined)."""
+    import multiprocessing as mp
+    P = host_cores()
+    flat = x_np.reshape(-1)
+    nblk = -(-flat.size // BLOCK)
+    cuts = [(nblk * i // P) * BLOCK for i in range(P + 1)]
+    cuts[-1] = flat.size
+    try:
+        cpus = sorted(os.sched_getaffinity(0))[:P]
+    except AttributeError:
+        cpus = [None] * P
+    tasks = [(flat[cuts[i]:cuts[i + 1]].copy(), bounds, BLOCK, seconds, cpus[i]) for i in range(P)]
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(P) as pool:
+        t0 = time.perf_counter()
+        res = pool.map(_oracle_worker, tasks)
+        wall = time.perf_counter() - t0
+    done = sum(r[0] for r in res)
+    return {"value": round(done / wall / 1e9, 4), "cores": P, "seconds": round(wall, 3),
+            "sample": f"{P} processes, one per core, each on a contiguous 1/{P} block range of the field, "
+                      f"compress + decompress at every bound repeated for about {seconds:.0f} s"}
+
+
+def to_keys(s, W):
+    """Signed integers whose order is IEEE totalOrder, from the bit patterns s
+    (int32/int64 tensor) of W-bit floats; the map is its own inverse."""
+    return s ^ ((s >> (W - 1)) & ((1 << (W - 1)) - 1))
+
+
+def stream_stats(x, out, size):
+    """Block outcomes of one compressed stream (device tensors: the field x,
+    the stream buffer out, its size): fractions of constant, coded and raw
+    blocks, histograms of the kept bits K and of the 2-bit codes, and the
+    escalations of the error-control ladder, counted against eq. (4)'s first
+    rung K0 computed here from each block's extrema (a measurement only: the
+    stream is what the kernels wrote)."""
+    import struct
+    import torch
+    hdr = out[:96].cpu().numpy().tobytes()
+    dt_code, b = hdr[5], struct.unpack_from("<I", hdr, 8)[0]
+    e_bits, nblk, n_nc, mid_total = struct.unpack_from("<4Q", hdr, 64)
+    w = 4 if dt_code == 0 else 8
+    W, E, BIAS = (32, 8, 127) if w == 4 else (64, 11, 1023)
+    MANT = W - 1 - E
+    idt = torch.int32 if w == 4 else torch.int64
+
+    def a16(v):
+        return (v + 15) & ~15
+    st_off = 96
+    mu_off = a16(st_off + (nblk + 7) // 8)
+    k_off = a16(mu_off + nblk * w)
+    c_off = a16(k_off + n_nc)
+    state = out[st_off:st_off + (nblk + 7) // 8]
+    bits = ((state.to(torch.int32).unsqueeze(1) >> torch.arange(8, device=out.device)) & 1).reshape(-1)[:nblk]
+    K = out[k_off:k_off + n_nc].to(torch.int64)
+    raw = K == 0xFF
+    n_raw = int(raw.sum())
+    n = x.numel()
+    # codes of coded blocks over their valid values
+    codes = out[c_off:c_off + n_nc * (b // 4)].reshape(n_nc, b // 4).to(torch.int32)
+    shifts = torch.tensor([6, 4, 2, 0], device=out.device, dtype=torch.int32)
+    cv = ((codes.unsqueeze(2) >> shifts) & 3).reshape(n_nc, b)
+    nc_idx = torch.nonzero(bits).reshape(-1)
+    valid = torch.ones_like(cv, dtype=torch.bool)
+    if n % b and n_nc and int(nc_idx[-1]) == nblk - 1:
+        valid[-1, n % b:] = False
+    valid &= ~raw.unsqueeze(1)
+    code_hist = torch.bincount(cv[valid].reshape(-1).to(torch.int64), minlength=4).tolist()
+    K_hist = {int(k): int(c) for k, c in enumerate(torch.bincount(K, minlength=256).tolist()) if c}
+    # first rung of every non-constant block from its extrema
+    s = x.reshape(-1).view(idt)
+    pad = nblk * b - n
+    if pad:
+        s = torch.cat([s, s[-1:].expand(pad)])
+    key = to_keys(s.reshape(nblk, b), W)
+    kn = key.min(1).values[nc_idx]
+    kx = key.max(1).values[nc_idx]
+    mn = to_keys(kn, W).view(x.dtype)
+    mx = to_keys(kx, W).view(x.dtype)
+    fin = torch.isfinite(mn) & torch.isfinite(mx)
+    mu = 0.5 * mn + 0.5 * mx
+    r = torch.maximum((mx - mu).abs(), (mn - mu).abs())
+
+    def p_of(v_bits):
+        f = (v_bits >> MANT) & ((1 << E) - 1)
+        return torch.clamp(f, min=1) - BIAS
+    e = torch.tensor([e_bits], dtype=idt, device=out.device)  # e >= 0: the sign bit is clear
+    m0 = torch.clamp(p_of(r.view(idt)) - p_of(e), min=0)
+    K0 = torch.clamp(1 + E + m0, max=W).to(torch.int64)
+    coded = ~raw
+    up1 = int((coded & fin & (K == K0 + 1) & (K0 < W)).sum())
+    at0 = int((coded & fin & (K == K0)).sum())
+    raw_fail = int((raw & fin).sum())
+    return {
+        "blocks": int(nblk),
+        "constant_frac": round(1 - n_nc / max(nblk, 1), 6),
+        "coded_frac": round((n_nc - n_raw) / max(nblk, 1), 6),
+        "raw_frac": round(n_raw / max(nblk, 1), 6),
+        "K_hist": K_hist,
+        "code_hist": code_hist,
+        "ladder": {"first_rung": at0, "second_rung_K0_plus_1": up1, "raw_by_failure": raw_fail,
+                   "raw_non_finite": n_raw - raw_fail},
+        "mid_bytes": int(mid_total),
+    }
+
+
+def quality(x, y, e_bits, w):
+    """Max |x - x'| (and over e) and PSNR of eq. (7) over the finite values."""
+    import math
+    import struct
+    import torch
+    xd = x.reshape(-1).double()
+    yd = y.reshape(-1).double()
+    fin = torch.isfinite(xd)
+    d = (yd - xd)[fin]
+    mx = float(d.abs().max()) if d.numel() else 0.0
+    mse = float((d * d).mean()) if d.numel() else 0.0
+    rng = float(xd[fin].max() - xd[fin].min()) if d.numel() else 0.0
+    e = struct.unpack("<f" if w == 4 else "<d", struct.pack("<Q", e_bits)[:w])[0]
+    psnr = 20 * math.log10(rng / math.sqrt(mse)) if mse > 0 and rng > 0 else float("inf")
+    return {"max_abs_err": mx, "max_err_over_e": (mx / e) if e > 0 else (0.0 if mx == 0 else float("inf")),
+            "psnr_db": round(psnr, 3), "e": e}
+
+
+def measure_field(name, args, dev, cpu_leg):
+    """Compress + decompress one workload field at each of its bounds on the
+    GPU: graph-replayed steps (the round-trip value), per-direction timings,
+    per-kernel durations, whole-call algorithmic fractions, stream and
+    quality statistics; with cpu_leg, the oracle's check and timing."""
+    import struct
     import numpy as np
     import torch
     from paper_2201_13020_amd import synth, szx
 
-    assert torch.cuda.is_available(), "bench needs a GPU"
-    if args.field == "batch":
-        return bench_batch(args)
-    if args.field == "serve":
-        return bench_serve(args)
-    if args.field == "io":
-        return bench_io(args)
-    dev = torch.device("cuda:0")
-    global BOUNDS
-    field = FIELDS[args.field]
-    BOUNDS = field["bounds"]
+    field = FIELDS[name]
+    bounds = field["bounds"]
     shape = field["shape"]
-    x_np = synth.make(args.field)
+    t0 = time.perf_counter()
+    x_np = synth.make(name)
+    _log(f"{name}: generated {x_np.nbytes / 1e6:.0f} MB in {time.perf_counter() - t0:.1f} s")
     n = x_np.size
     w = x_np.itemsize
     nbytes = n * w
@@ -151,23 +327,15 @@ def main():
     xs = [torch.from_numpy(x_np).to(dev) for _ in range(C)]
     cap = szx.compress_bound(tdt, shape, 1e-3, "rel", BLOCK)
     wsz = szx.workspace_size(tdt, shape, 1e-3, "rel", BLOCK)
-    outs = {eb: [torch.empty(cap, dtype=torch.uint8, device=dev) for _ in range(C)] for eb in BOUNDS}
-    sizes = {eb: [torch.zeros(1, dtype=torch.uint64, device=dev) for _ in range(C)] for eb in BOUNDS}
+    outs = {eb: [torch.empty(cap, dtype=torch.uint8, device=dev) for _ in range(C)] for eb in bounds}
+    sizes = {eb: [torch.zeros(1, dtype=torch.uint64, device=dev) for _ in range(C)] for eb in bounds}
     ys = [torch.empty(n, dtype=tdt, device=dev) for _ in range(C)]
     stat = torch.zeros(1, dtype=torch.uint32, device=dev)
     ws = torch.empty(wsz, dtype=torch.uint8, device=dev)
     expected = dict(dtype=tdt, dims=shape, block=BLOCK)
 
-    # first pass: stream sizes (the decoder reads only what the header says,
-    # but the in_bytes argument must cover the stream)
-    stream_len = {}
-    for eb in BOUNDS:
-        szx.compress(xs[0], eb, "rel", BLOCK, out=outs[eb][0], out_size=sizes[eb][0], ws=ws)
-        torch.cuda.synchronize()
-        stream_len[eb] = int(sizes[eb][0].cpu().view(torch.int64).item())
-
     def step(c, timed_ops=None):
-        for eb in BOUNDS:
+        for eb in bounds:
             if timed_ops is not None:
                 timed_ops[eb][0].record()
             szx.compress(xs[c], eb, "rel", BLOCK, out=outs[eb][c], out_size=sizes[eb][c], ws=ws)
@@ -177,48 +345,67 @@ def main():
             if timed_ops is not None:
                 timed_ops[eb][2].record()
 
-    # correctness against the CPU oracle (also the CPU baseline timing)
-    cpu = None
-    ratios = {}
-    step(0)
-    torch.cuda.synchronize()
-    for eb in BOUNDS:
+    # stream statistics and reconstruction quality, one bound at a time
+    stream_len, ratios, per_bound = {}, {}, {}
+    for eb in bounds:
+        szx.compress(xs[0], eb, "rel", BLOCK, out=outs[eb][0], out_size=sizes[eb][0], ws=ws)
+        szx.decompress(outs[eb][0], cap, expected, out=ys[0], status=stat, ws=ws)
+        torch.cuda.synchronize()
+        assert int(stat.cpu().view(torch.int32).item()) == 0, f"{name} eb={eb}: decoder status"
+        stream_len[eb] = int(sizes[eb][0].cpu().view(torch.int64).item())
         ratios[eb] = nbytes / stream_len[eb]
-    if not args.no_cpu_baseline and not args.profile:
+        e_bits = struct.unpack_from("<Q", outs[eb][0][:96].cpu().numpy().tobytes(), 64)[0]
+        q = quality(xs[0], ys[0], e_bits, w)
+        assert q["max_err_over_e"] <= 1.0, f"{name} eb={eb}: error above the bound"
+        per_bound[eb] = {"quality": q, "blocks": stream_stats(xs[0], outs[eb][0], sizes[eb][0])}
+    _log(f"{name}: ratios {', '.join(f'{r:.3f}' for r in ratios.values())}")
+
+    # correctness against the CPU oracle (also the single-thread CPU timing)
+    cpu = None
+    if cpu_leg:
         from oracle import szref
+        step(0)
+        torch.cuda.synchronize()
+        try:
+            aff = os.sched_getaffinity(0)
+            os.sched_setaffinity(0, {min(aff)})
+        except (AttributeError, OSError):
+            aff = None
         # the whole workload, repeated until about 10 s of CPU time (the
         # first pass also checks the GPU results against the oracle)
         t_c = t_d = 0.0
         passes = 0
-        while passes == 0 or (t_c + t_d < 10.0 and passes < 64):
-            for eb in BOUNDS:
-                t0 = time.perf_counter()
-                ref = szref.compress(x_np, eb, "rel", BLOCK)
-                t1 = time.perf_counter()
-                yref = szref.decompress(ref)
-                t2 = time.perf_counter()
-                t_c += t1 - t0
-                t_d += t2 - t1
+        try:
+            while passes == 0 or (t_c + t_d < 10.0 and passes < 64):
+                for eb in bounds:
+                    t0 = time.perf_counter()
+                    ref = szref.compress(x_np, eb, "rel", BLOCK)
+                    t1 = time.perf_counter()
+                    yref = szref.decompress(ref)
+                    t2 = time.perf_counter()
+                    t_c += t1 - t0
+                    t_d += t2 - t1
+                    if passes == 0:
+                        gpu_stream = outs[eb][0][: stream_len[eb]].cpu().numpy()
+                        assert gpu_stream.size == ref.size and np.array_equal(gpu_stream, ref), \
+                            f"GPU stream differs from the oracle at eb={eb}"
                 if passes == 0:
-                    gpu_stream = outs[eb][0][: stream_len[eb]].cpu().numpy()
-                    assert gpu_stream.size == ref.size and np.array_equal(gpu_stream, ref), \
-                        f"GPU stream differs from the oracle at eb={eb}"
-            if passes == 0:
-                y_last = ys[0].cpu().numpy()
-                udt = np.uint32 if w == 4 else np.uint64
-                assert np.array_equal(y_last.view(udt), yref.ravel().view(udt)), "GPU decode differs from the oracle"
-            passes += 1
-        done = passes * len(BOUNDS) * nbytes
-        cpu = {
+                    y_last = ys[0].cpu().numpy()
+                    udt = np.uint32 if w == 4 else np.uint64
+                    assert np.array_equal(y_last.view(udt), yref.ravel().view(udt)), \
+                        "GPU decode differs from the oracle"
+                passes += 1
+        finally:
+            if aff is not None:
+                os.sched_setaffinity(0, aff)
+        done = passes * len(bounds) * nbytes
+        cpu = {"single_thread": {
             "value": round(done / (t_c + t_d) / 1e9, 4),
-            "unit": "GB/s",
-            "cores": 1,
-            "kind": "oracle",
-            "sample": f"whole workload {passes} times: {field['desc']}, REL {', '.join(map(str, BOUNDS))}, "
-                      f"compress + decompress each, single thread; compress {done / t_c / 1e6:.0f} MB/s, "
-                      f"decompress {done / t_d / 1e6:.0f} MB/s",
-            "seconds": round(t_c + t_d, 3),
-        }
+            "compress_MBps": round(done / t_c / 1e6, 1), "decompress_MBps": round(done / t_d / 1e6, 1),
+            "passes": passes, "seconds": round(t_c + t_d, 3)}}
+        _log(f"{name}: oracle single thread matched; {cpu['single_thread']}")
+        cpu["all_cores"] = cpu_all_cores(x_np, bounds)
+        _log(f"{name}: oracle all cores {cpu['all_cores']}")
 
     # graphs, one per copy
     graphs = None
@@ -247,98 +434,146 @@ def main():
     for i in range(args.warmup):
         run(i % C)
     torch.cuda.synchronize()
-
     # timed region
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
         run(i % C)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    ms_per_step = elapsed * 1e3 / args.steps
-    value = len(BOUNDS) * nbytes / (elapsed / args.steps) / 1e9
-
-    # check the last replays decoded correctly (status and a spot check)
     assert int(stat.cpu().view(torch.int32).item()) == 0
+    res = {"name": name, "desc": field["desc"], "bounds": bounds, "n": n, "w": w, "nbytes": nbytes, "copies": C,
+           "launch": "eager" if graphs is None else "hip graph replay",
+           "ms_per_step": elapsed * 1e3 / args.steps,
+           "value": len(bounds) * nbytes / (elapsed / args.steps) / 1e9, "cpu": cpu}
+    if args.profile:
+        return res
 
+    facts = {}
+    for eb in bounds:
+        facts[eb] = struct.unpack_from("<3Q", outs[eb][0][:96].cpu().numpy().tobytes(), 72)
+    # per-direction timings: events between the calls on the same stream
+    ev = {eb: [torch.cuda.Event(enable_timing=True) for _ in range(3)] for eb in bounds}
+    tc = {eb: 0.0 for eb in bounds}
+    td = {eb: 0.0 for eb in bounds}
+    for i in range(args.steps):
+        step(i % C, ev)
+        torch.cuda.synchronize()
+        for eb in bounds:
+            tc[eb] += ev[eb][0].elapsed_time(ev[eb][1])
+            td[eb] += ev[eb][1].elapsed_time(ev[eb][2])
+    detail = {}
+    for eb in bounds:
+        c_ms = tc[eb] / args.steps
+        d_ms = td[eb] / args.steps
+        nblk, n_nc, mid_total = facts[eb]
+        C_bytes = stream_len[eb]
+        f_nc = n_nc / max(nblk, 1)
+        alg_c = nbytes * (1 + f_nc) + C_bytes  # REL: the range pass reads all, the encoder re-reads non-constant blocks
+        alg_d = C_bytes + nbytes
+        detail[str(eb)] = {
+            "ratio": round(ratios[eb], 4),
+            "compress_GBps": round(nbytes / c_ms / 1e6, 1),
+            "decompress_GBps": round(nbytes / d_ms / 1e6, 1),
+            "compress_ms": round(c_ms, 4),
+            "decompress_ms": round(d_ms, 4),
+            "compress_hbm_frac_uncompressed": round(nbytes / c_ms / 1e6 / HBM_PEAK_GBPS, 4),
+            "decompress_hbm_frac_uncompressed": round(nbytes / d_ms / 1e6 / HBM_PEAK_GBPS, 4),
+            "compress_alg_bytes": int(alg_c),
+            "decompress_alg_bytes": int(alg_d),
+            "compress_hbm_frac_alg": round(alg_c / c_ms / 1e6 / HBM_PEAK_GBPS, 4),
+            "decompress_hbm_frac_alg": round(alg_d / d_ms / 1e6 / HBM_PEAK_GBPS, 4),
+            **per_bound[eb],
+        }
+    res["per_bound"] = detail
+
+    # per-kernel durations with HIP events around each launch (same stream)
+    szx.timing_enable(True)
+    szx.timing_read()
+    for i in range(args.steps):
+        step(i % C)
+    torch.cuda.synchronize()
+    kt = szx.timing_read()
+    szx.timing_enable(False)
+    kernels = {}
+    for kname, (cnt, ms) in kt.items():
+        # each kernel runs once per bound per step: average algorithmic bytes over the bounds
+        alg = sum(kernel_bytes(kname, n, w, *facts[eb]) for eb in bounds) / len(bounds)
+        avg_ms = ms / cnt
+        kernels[kname] = {"launches": cnt, "avg_us": round(avg_ms * 1e3, 2), "alg_bytes_per_launch": int(alg),
+                          "achieved_GBps": round(alg / avg_ms / 1e6, 1) if alg else None}
+    res["kernels"] = kernels
+    return res
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1 (sharding over several GPUs is a design, not built)"}))
+        sys.exit(2)
+    import torch
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    if args.field == "batch":
+        return bench_batch(args)
+    if args.field == "serve":
+        return bench_serve(args)
+    if args.field == "io":
+        return bench_io(args)
+    dev = torch.device("cuda:0")
+    cpu_leg = not args.no_cpu_baseline and not args.profile
+    head = measure_field(args.field, args, dev, cpu_leg)
+    bounds = head["bounds"]
     result = {
         "metric": "compress & decompress GB/s (uncompressed) and % of HBM peak; ratio",
-        "value": round(value, 2),
+        "value": round(head["value"], 2),
         "unit": "GB/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step": round(head["ms_per_step"], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if w == 4 else "f64",
+        "dtype": "f32" if head["w"] == 4 else "f64",
         "data": "synthetic",
-        "config": {"workload": f"{field['desc']}, REL {', '.join(map(str, BOUNDS))}, block {BLOCK}; "
+        "config": {"workload": f"{head['desc']}, REL {', '.join(map(str, bounds))}, block {BLOCK}; "
                                "one step = compress + decompress at each bound",
-                   "global_batch": len(BOUNDS), "elements": n, "block": BLOCK, "parallelism": "single GPU",
-                   "launch": "eager" if graphs is None else "hip graph replay", "input_copies": C},
+                   "global_batch": len(bounds), "elements": head["n"], "block": BLOCK,
+                   "parallelism": "single GPU", "launch": head["launch"], "input_copies": head["copies"]},
     }
-
     if not args.profile:
-        # per-direction timings with events between the calls
-        ev = {eb: [torch.cuda.Event(enable_timing=True) for _ in range(3)] for eb in BOUNDS}
-        tc = {eb: 0.0 for eb in BOUNDS}
-        td = {eb: 0.0 for eb in BOUNDS}
-        for i in range(args.steps):
-            step(i % C, ev)
-            torch.cuda.synchronize()
-            for eb in BOUNDS:
-                tc[eb] += ev[eb][0].elapsed_time(ev[eb][1])
-                td[eb] += ev[eb][1].elapsed_time(ev[eb][2])
-        detail = {}
-        for eb in BOUNDS:
-            c_ms = tc[eb] / args.steps
-            d_ms = td[eb] / args.steps
-            detail[str(eb)] = {
-                "ratio": round(ratios[eb], 4),
-                "compress_GBps": round(nbytes / c_ms / 1e6, 1),
-                "decompress_GBps": round(nbytes / d_ms / 1e6, 1),
-                "compress_ms": round(c_ms, 4),
-                "decompress_ms": round(d_ms, 4),
-                "compress_hbm_frac_uncompressed": round(nbytes / c_ms / 1e6 / HBM_PEAK_GBPS, 4),
-                "decompress_hbm_frac_uncompressed": round(nbytes / d_ms / 1e6 / HBM_PEAK_GBPS, 4),
-            }
-        result["detail"] = {"eager_launch_per_direction": detail}
-
-        # per-kernel durations with HIP events around each launch (same stream)
-        szx.timing_enable(True)
-        szx.timing_read()
-        for i in range(args.steps):
-            step(i % C)
-        torch.cuda.synchronize()
-        kt = szx.timing_read()
-        szx.timing_enable(False)
-        # stream facts for the algorithmic bytes
-        import struct
-        facts = {}
-        for eb in BOUNDS:
-            hdr = outs[eb][0][:96].cpu().numpy().tobytes()
-            nblk, n_nc, mid_total = struct.unpack_from("<3Q", hdr, 72)
-            facts[eb] = (nblk, n_nc, mid_total)
-        kernels = {}
-        for name, (cnt, ms) in kt.items():
-            # each kernel runs once per bound per step: average algorithmic bytes over the bounds
-            alg = sum(kernel_bytes(name, n, w, *facts[eb]) for eb in BOUNDS) / len(BOUNDS)
-            avg_ms = ms / cnt
-            kernels[name] = {"launches": cnt, "avg_us": round(avg_ms * 1e3, 2),
-                             "alg_bytes_per_launch": int(alg),
-                             "achieved_GBps": round(alg / avg_ms / 1e6, 1) if alg else None}
-        result["detail"]["kernels"] = kernels
-        dom = max((k for k in kernels if kernels[k]["alg_bytes_per_launch"]), key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches"])
+        kernels = head["kernels"]
+        result["detail"] = {"per_bound": head["per_bound"], "kernels": kernels}
+        dom = max((k for k in kernels if kernels[k]["alg_bytes_per_launch"]),
+                  key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches"])
         kd = kernels[dom]
         result["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": kd["achieved_GBps"],
                               "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                               "frac": round(kd["achieved_GBps"] / HBM_PEAK_GBPS, 4),
                               "traffic": recorded_traffic(dom, args.field),
                               "alg_bytes_per_launch": kd["alg_bytes_per_launch"], "avg_launch_us": kd["avg_us"]}
+        if args.field == "turbulence" and not args.no_state:
+            # the 2 GiB float64 field, timed in the same run (graph replay)
+            st = measure_field("state", args, dev, False)
+            result["detail"]["state_2p28_float64"] = {
+                "workload": f"{st['desc']}, REL {', '.join(map(str, st['bounds']))}, block {BLOCK}",
+                "round_trip_GBps": round(st["value"], 2), "ms_per_step": round(st["ms_per_step"], 4),
+                "launch": st["launch"], "input_copies": st["copies"],
+                "per_bound": st["per_bound"], "kernels": st["kernels"]}
+    cpu = head["cpu"]
     if cpu is not None:
-        result["cpu_baseline"] = cpu
+        single, allc = cpu["single_thread"], cpu["all_cores"]
+        result["cpu_baseline"] = {
+            "value": allc["value"], "unit": "GB/s", "cores": allc["cores"], "kind": "oracle",
+            "sample": f"{head['desc']}, REL {', '.join(map(str, bounds))}: {allc['sample']}; "
+                      f"bytes compressed per second of compress + decompress, as for the GPU value",
+            "cpu_model": cpu_model(),
+            "single_thread": {"value": single["value"], "unit": "GB/s", "cores": 1,
+                              "compress_MBps": single["compress_MBps"],
+                              "decompress_MBps": single["decompress_MBps"],
+                              "sample": f"whole workload {single['passes']} times on one pinned core, "
+                                        f"{single['seconds']} s; the first pass matched the GPU byte for byte"},
+            "seconds": allc["seconds"]}
 
     if args.profile:
         # a plain device copy of known size, to scale the HBM byte counters
