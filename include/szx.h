@@ -79,7 +79,15 @@ uint64_t sz_compress_bound(const sz_params* p);
 /* Device workspace in bytes that sz_compress and sz_decompress need for these
    parameters (per-block extrema, the list of non-constant blocks, tile status
    words of the single-pass scans, counters). 0 if the parameters are invalid.
-   Host only, pure. The workspace holds no state between calls. */
+   Host only, pure. A workspace may hold any bytes before its first use.
+   Between compressions its first SZ_WS_KEPT_BYTES bytes carry state from one
+   call to the next (the global range pass's slots, left zero, and a word
+   that marks them so, at the same offsets for every field size); a
+   compression that does not find that mark takes a slower path that does
+   not trust the slots, and leaves the mark for the next call. Do not write
+   into those bytes between calls (overwriting the whole workspace, its first
+   bytes included, is fine). sz_decompress does not touch them. */
+#define SZ_WS_KEPT_BYTES 16640
 uint64_t sz_workspace_size(const sz_params* p);
 
 /* Compress N values of p->dtype at d_in (device, 16-byte aligned) into d_out

@@ -14,6 +14,8 @@
 #include "../../include/szx.h"
 #include "szx_host.hpp"
 
+static_assert(SZ_WS_KEPT_BYTES == szx::kSlotRegionBytes, "the header states the bytes a workspace keeps");
+
 namespace szx {
 namespace host {
 
@@ -133,8 +135,10 @@ szx::FieldC single_field_c(const szx::Job& j, const void* in, void* out, uint64_
   f.ndims = j.ndims;
   f.b = j.b;
   f.ctr = (szx::Counters*)(ws + W.counters);
+  f.clean = (uint64_t*)(ws + W.clean);
   f.range = (uint64_t*)(ws + W.range);
   f.nslots = szx::range_slots(ft.chunks);
+  f.parts = (uint64_t*)(ws + W.parts);
   f.stats = ws + W.stats;
   f.plan = ws + W.plan;
   f.enc_r0 = (uint64_t*)(ws + W.enc_r0);
@@ -239,22 +243,31 @@ sz_status plan_compress(const sz_cfield* fs, uint32_t n, uint8_t* ws, std::vecto
     P.maps_off[m] = off;
     off = a256(off + P.tiles[m] * 4);
   }
+  // clean words and range slots: part of the image written at planning
+  // (marked clean), kept clean by every run
+  std::vector<uint64_t> slot_off(n);
+  for (uint32_t i = 0; i < n; ++i) {
+    slot_off[i] = off;
+    off = a256(off + szx::kSlotRegionBytes);
+  }
   P.zero_off = off;
   off = a256(off + 2ull * szx::kTicketClasses * 256);  // tickets
   std::vector<uint64_t> ctr_off(n), cls_off(n), mid_off(n);
   for (uint32_t i = 0; i < n; ++i) {
     const szx::FieldTiles ft = szx::field_tiles(jobs[i].n, jobs[i].nblk, jobs[i].w, block);
     ctr_off[i] = off;
-    off = a256(off + 256 + (uint64_t)szx::range_slots(ft.chunks) * szx::kRangeStride);
+    off = a256(off + 256);
     cls_off[i] = off;
     off = a256(off + (ft.cls + 1) * 8);
     mid_off[i] = off;
     off = a256(off + (ft.enc + 1) * 8);
   }
   P.zero_end = off;
-  std::vector<uint64_t> stats_off(n), plan_off(n), r0_off(n);
+  std::vector<uint64_t> parts_off(n), stats_off(n), plan_off(n), r0_off(n);
   for (uint32_t i = 0; i < n; ++i) {
     const szx::FieldTiles ft = szx::field_tiles(jobs[i].n, jobs[i].nblk, jobs[i].w, block);
+    parts_off[i] = off;
+    off = a256(off + ft.chunks * 16);
     stats_off[i] = off;
     off = a256(off + jobs[i].nblk * 2 * (uint64_t)jobs[i].w);
     plan_off[i] = off;
@@ -269,6 +282,7 @@ sz_status plan_compress(const sz_cfield* fs, uint32_t n, uint8_t* ws, std::vecto
   uint32_t* maps[6];
   for (int m = 0; m < 6; ++m) maps[m] = (uint32_t*)(host->data() + P.maps_off[m]);
   uint64_t bc[2] = {0, 0}, bl[2] = {0, 0}, be[2] = {0, 0};
+  uint32_t any_empty = 0;
   for (uint32_t i = 0; i < n; ++i) {
     const szx::Job& j = jobs[i];
     const sz_cfield& c = fs[i];
@@ -292,8 +306,11 @@ sz_status plan_compress(const sz_cfield* fs, uint32_t n, uint8_t* ws, std::vecto
     f.ndims = j.ndims;
     f.b = j.b;
     f.ctr = (szx::Counters*)(ws + ctr_off[i]);
-    f.range = (uint64_t*)(ws + ctr_off[i] + 256);
+    f.clean = (uint64_t*)(ws + slot_off[i]);
+    f.range = (uint64_t*)(ws + slot_off[i] + 256);
     f.nslots = szx::range_slots(ft.chunks);
+    f.parts = (uint64_t*)(ws + parts_off[i]);
+    *(uint64_t*)(host->data() + slot_off[i]) = szx::kCleanWord;
     f.stats = ws + stats_off[i];
     f.plan = ws + plan_off[i];
     f.enc_r0 = (uint64_t*)(ws + r0_off[i]);
@@ -308,6 +325,7 @@ sz_status plan_compress(const sz_cfield* fs, uint32_t n, uint8_t* ws, std::vecto
     for (uint64_t t = 0; t < ft.cls; ++t) maps[2 + dt][bl[dt] + t] = i;
     for (uint64_t t = 0; t < ft.enc; ++t) maps[4 + dt][be[dt] + t] = i;
     bc[dt] += ft.chunks;
+    if (j.nblk == 0) any_empty = 1;
     bl[dt] += ft.cls;
     be[dt] += ft.enc;
   }
@@ -326,6 +344,7 @@ sz_status plan_compress(const sz_cfield* fs, uint32_t n, uint8_t* ws, std::vecto
   b.zero_begin = (uint64_t*)(ws + P.zero_off);
   b.zero_words = (P.zero_end - P.zero_off) / 8;
   b.nfields = n;
+  b.any_empty = any_empty;
   *block_out = block;
   return SZ_OK;
 }
@@ -464,8 +483,9 @@ sz_status sz_compress(const sz_params* p, const void* d_in, void* d_out, uint64_
   b.tiles_enc[j.dtype] = ft.enc;
   b.tickets = (uint32_t*)(ws + W.tickets);
   b.zero_begin = (uint64_t*)(ws + W.counters);
-  b.zero_words = (W.zero_end - W.counters) / 8;
+  b.zero_words = (W.dec_rank - W.counters) / 8;
   b.nfields = 1;
+  b.any_empty = j.nblk == 0;
   szx::CLaunchGeom g;
   g.encode_wgs[0] = g.encode_wgs[1] = encode_wgs_for(j.dtype, j.n * j.w, ncu);
   const hipError_t e = szx::launch_compress(b, j.b, g, stream, current_hook());
@@ -524,8 +544,8 @@ sz_status sz_compress_noalloc(const sz_params* p, const void* d_in, void* d_out,
   void* ptr = nullptr;
   s = scratch_of_current_device(&ptr);
   if (s != SZ_OK) return s;
-  // the same kernels as sz_compress; they clear the workspace words that must
-  // start at zero (counters, range slots, tickets, scan status words) first
+  // the same kernels as sz_compress; their first pass clears the workspace
+  // words that must start at zero (counters, tickets, scan status words)
   return sz_compress(p, d_in, d_out, out_cap, d_out_size, ptr, SZ_NOALLOC_SCRATCH_BYTES, stream);
 }
 

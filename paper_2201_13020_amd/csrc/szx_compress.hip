@@ -3,15 +3,18 @@
 // Pipeline of one sz_compress call, or of one batch of fields (all on the
 // caller's stream; every pass is one launch over all fields of the batch, a
 // single call being a batch of one, so both run the same code):
-//   k_init      clear counters, tickets and the tile status words of the scans
-//   k_stats     per-block totalOrder min/max (Alg. 1 needs both for mu_k); each
-//               workgroup folds its finite value range into the field's
-//               counters (two 64-bit atomic maxima)
+//   k_stats     clears the counters, tickets and tile status words the later
+//               passes use; per-block totalOrder min/max (Alg. 1 needs both
+//               for mu_k); each workgroup folds its finite value range into
+//               one of the field's range slots (two 64-bit atomic maxima)
 //   k_classify  the absolute bound e (for the relative bound: eb times the
-//               field's finite range, Sec. III footnote), then
-//               mid-range mu and constant test of every block (Alg. 1), the
-//               state bits and the mu section; a light single-pass prefix count
-//               of non-constant blocks gives each encode tile its first rank
+//               field's finite range, Sec. III footnote -- every wave folds
+//               the range slots itself), then mid-range mu and constant test
+//               of every block (Alg. 1), the state bits and the mu section; a
+//               light single-pass prefix count of non-constant blocks gives
+//               each encode tile its first rank. The field's last tile writes
+//               the header (all but the mid-byte total) and the section
+//               padding, and leaves the range slots zero for the next call.
 //   k_encode    per non-constant block: normalise, keep K bits (eq. (4)), shift
 //               (eq. (5)), verify the bound where it is not proved a priori,
 //               2-bit leading-byte codes and mid bytes. Persistent workgroups
@@ -20,13 +23,21 @@
 //               from a single-pass prefix sum over its field's tiles (Sec. V-B),
 //               and while a tile waits for it the next tile's data is loaded.
 //               Bytes are packed in LDS and leave in aligned 16-byte stores.
-//   k_finalize  header, section padding, stream size; one workgroup a field
+//               A single call's last tile, once its offset is known, writes
+//               the mid-byte total and the stream size.
+//   k_finalize  batches: every field's mid-byte total and stream size, and
+//               the header of fields without values (a single call only
+//               runs it when its field has no values)
 #include <algorithm>
 
 #include "szx_device.hpp"
 #include "szx_launch.hpp"
 
 namespace szx {
+
+// The stream size while a compression runs (the classification pass sets
+// it, the field's last encode tile replaces it).
+constexpr uint64_t kSizePending = ~0ull;
 
 // Field of a call, or of a batch entry, as the kernels see it (a copy with
 // its pointers typed as global memory).
@@ -40,7 +51,9 @@ __device__ __forceinline__ FieldC field_at(const CBatch& b, uint32_t fi) {
   f.out = as_global(f.out);
   f.out_size = as_global(f.out_size);
   f.ctr = as_global(f.ctr);
+  f.clean = as_global(f.clean);
   f.range = as_global(f.range);
+  f.parts = as_global(f.parts);
   f.stats = as_global(f.stats);
   f.plan = as_global(f.plan);
   f.enc_r0 = as_global(f.enc_r0);
@@ -51,14 +64,6 @@ __device__ __forceinline__ FieldC field_at(const CBatch& b, uint32_t fi) {
 template <int BATCH = kAnyCall>
 __device__ __forceinline__ uint32_t field_of(const uint32_t* map, uint64_t t) {
   return BATCH == kSingle ? 0u : BATCH == kBatch ? map[t] : (map ? map[t] : 0u);
-}
-
-// ------------------------------------------------------------------ init ---
-
-__global__ __launch_bounds__(256) void k_init(CBatch b) {
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < b.zero_words; i += stride)
-    b.zero_begin[i] = 0;
 }
 
 // Load EPL consecutive values starting at element i0 (aligned to EPL); values
@@ -214,6 +219,11 @@ __device__ __forceinline__ void stats_tile(const T (&v)[Geo<T, B>::EPL], int cnt
   }
 }
 
+// Per-block totalOrder extrema (as keys) of all values over a chunk of
+// kStatsChunk tiles of one field (two tiles per iteration keep more loads in
+// flight), and the chunk's finite range folded into one of the field's range
+// slots -- or, on the field's first use of the workspace, stored as the
+// chunk's partial.
 template <typename T, int B>
 __device__ __forceinline__ void stats_chunk(const FieldC& f, uint64_t c, uint64_t* s_lo, uint64_t* s_hi) {
   using U = typename Traits<T>::U;
@@ -249,7 +259,10 @@ __device__ __forceinline__ void stats_chunk(const FieldC& f, uint64_t c, uint64_
       lo = s_lo[i] < lo ? s_lo[i] : lo;
       hi = s_hi[i] > hi ? s_hi[i] : hi;
     }
-    if (lo <= hi) {  // the chunk saw a finite value
+    if (*f.clean != kCleanWord) {
+      // lo > hi: no finite value
+      *reinterpret_cast<ulonglong2*>(f.parts + 2 * c) = make_ulonglong2(lo, hi);
+    } else if (lo <= hi) {  // the chunk saw a finite value
       uint64_t* slot = f.range + (c % f.nslots) * (kRangeStride / 8);
       atomicMax((unsigned long long*)slot, ~(unsigned long long)lo);
       atomicMax((unsigned long long*)slot + 1, (unsigned long long)hi);
@@ -257,33 +270,87 @@ __device__ __forceinline__ void stats_chunk(const FieldC& f, uint64_t c, uint64_
   }
 }
 
+// Before any work, every extrema workgroup (of both element types) clears
+// its slice of the words that the later passes count, publish and wait on:
+// they run after this pass, and nothing in it reads them.
 template <typename T, int B>
 __global__ __launch_bounds__(256) void k_stats(CBatch b) {
   __shared__ uint64_t s_lo[kWavesPerWG], s_hi[kWavesPerWG];
+  constexpr int DT = sizeof(T) == 4 ? 0 : 1;
   const uint64_t g = blockIdx.x;
-  const FieldC f = field_at(b, field_of(b.field_stats[Traits<T>::BYTES / 8], g));
+  const uint64_t all = b.tiles_stats[0] + b.tiles_stats[1];
+  for (uint64_t i = ((DT ? b.tiles_stats[0] : 0) + g) * kWG + threadIdx.x; i < b.zero_words; i += all * kWG)
+    b.zero_begin[i] = 0;
+  const FieldC f = field_at(b, field_of(b.field_stats[DT], g));
   stats_chunk<T, B>(f, g - f.base_stats, s_lo, s_hi);
 }
 
 // ----------------------------------------------------------------- range ---
 
-// The bound e of a field (as the bits of a T) from its parameters and, for
-// the relative bound, the field's finite range that the extrema pass folded
-// into its range slots (no finite value: the range is empty and e = 0). Each
-// wave folds the slots by itself, one per lane: no barrier.
-__device__ __forceinline__ uint64_t bound_bits(const FieldC& f) {
+__device__ __forceinline__ uint64_t bound_of(const FieldC& f, uint64_t lo, uint64_t hi) {
   const int rel = f.eb_mode == 1;
-  uint64_t lo_inv = 0, hi = 0;
-  const uint32_t l = lane_id();
-  if (rel && l < f.nslots) {
-    lo_inv = f.range[l * (kRangeStride / 8)];
-    hi = f.range[l * (kRangeStride / 8) + 1];
-  }
-  lo_inv = group_max<kWave, uint64_t>(lo_inv);
-  hi = group_max<kWave, uint64_t>(hi);
-  const uint64_t lo = ~lo_inv;
   return f.dtype == 0 ? (uint64_t)bits_of(bound_from<float>(rel, f.eb, lo, hi))
                       : (uint64_t)bits_of(bound_from<double>(rel, f.eb, lo, hi));
+}
+
+// The bound e of a field (as the bits of a T) from its parameters and, for
+// the relative bound, the field's finite range (no finite value: the range
+// is empty and e = 0). Every thread of classification tile t calls it.
+// Range slots in use (clean): each wave folds them by itself, one per lane.
+// First use: tile t = 0 folds the chunks' partials and publishes the bound
+// in the counters; the other tiles wait for it (tile 0 waits on nothing, and
+// a workgroup runs only once every lower-numbered one has been dispatched).
+// Contains a barrier on the first-use path of tile 0.
+__device__ __forceinline__ uint64_t field_bound(const FieldC& f, uint32_t t, bool clean, uint64_t nchunks,
+                                               uint64_t* s_red) {
+  if (f.eb_mode != 1) return bound_of(f, ~0ull, 0ull);  // absolute bound: no range needed
+  const uint32_t l = lane_id();
+  if (clean) {
+    uint64_t lo_inv = 0, hi = 0;
+    if (l < f.nslots) {
+      lo_inv = f.range[l * (kRangeStride / 8)];
+      hi = f.range[l * (kRangeStride / 8) + 1];
+    }
+    lo_inv = group_max<kWave, uint64_t>(lo_inv);
+    hi = group_max<kWave, uint64_t>(hi);
+    return bound_of(f, ~lo_inv, hi);
+  }
+  if (t == 0) {
+    uint64_t lo = ~0ull, hi = 0;
+    for (uint64_t i = threadIdx.x; i < nchunks; i += kWG) {
+      const ulonglong2 p = reinterpret_cast<const ulonglong2*>(f.parts)[i];
+      lo = p.x < lo ? p.x : lo;
+      hi = p.y > hi ? p.y : hi;
+    }
+    lo = group_min<kWave, uint64_t>(lo);
+    hi = group_max<kWave, uint64_t>(hi);
+    const int w = threadIdx.x / kWave;
+    if (l == 0) {
+      s_red[2 * w] = lo;
+      s_red[2 * w + 1] = hi;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kWavesPerWG; ++i) {
+      lo = s_red[2 * i] < lo ? s_red[2 * i] : lo;
+      hi = s_red[2 * i + 1] > hi ? s_red[2 * i + 1] : hi;
+    }
+    const uint64_t e_bits = bound_of(f, lo, hi);
+    if (threadIdx.x == 0) {
+      f.ctr->e_bits = e_bits;
+      __hip_atomic_store(&f.ctr->e_ready, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return e_bits;
+  }
+  uint32_t spins = 0;
+  while (__hip_atomic_load(&f.ctr->e_ready, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+    if (++spins > kSpinLimit) {
+      if (l == 0) atomicMax(&f.ctr->err, 1u);
+      return 0;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+  return __hip_atomic_load(&f.ctr->e_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Parameters of one block from its totalOrder extrema (keys): K = -1 for a
@@ -334,6 +401,51 @@ __device__ __forceinline__ uint32_t plan_byte(const BlockPlan<T>& p) {
   return p.K < 0 ? 0xFFu : (uint32_t)p.K | (p.verify ? 0x80u : 0u);
 }
 
+// ---------------------------------------------------------------- header ---
+
+// Header and the zero padding after the state bits, mu, K and codes sections
+// of a field's stream, by the threads of one workgroup. Returns the stream
+// size.
+__device__ __forceinline__ uint64_t write_stream_header(const FieldC& f, uint64_t e_bits, uint64_t n_nc,
+                                                        uint64_t mid_total) {
+  const uint32_t w = f.dtype == 0 ? 4 : 8;
+  const Sections s = sections(f.nblk, n_nc, w, f.b, mid_total);
+  uint8_t* out = f.out;
+  if (threadIdx.x == 0) {
+    uint32_t* o32 = reinterpret_cast<uint32_t*>(out);
+    uint64_t* o64 = reinterpret_cast<uint64_t*>(out);
+    o32[0] = kMagic;
+    o32[1] = (uint32_t)kVersion | (f.dtype << 8) | (f.eb_mode << 16) | (f.ndims << 24);
+    o32[2] = f.b;
+    o32[3] = 0;
+    for (int d = 0; d < 4; ++d) o64[2 + d] = f.dims[d];
+    o64[6] = f.n;
+    o64[7] = (uint64_t)__double_as_longlong(f.eb);
+    o64[8] = e_bits;
+    o64[9] = f.nblk;
+    o64[10] = n_nc;
+    o64[11] = mid_total;
+  }
+  const uint64_t pads[4][2] = {{96 + cdiv(f.nblk, 8), s.mu},
+                               {s.mu + f.nblk * w, s.kbytes},
+                               {s.kbytes + n_nc, s.codes},
+                               {s.codes + n_nc * (f.b / 4), s.mid}};
+  for (int p = 0; p < 4; ++p)
+    for (uint64_t i = pads[p][0] + threadIdx.x; i < pads[p][1]; i += blockDim.x) out[i] = 0;
+  return s.total;
+}
+
+// The end of a field's stream, by its last encode tile once that tile's
+// offset is known: the mid-byte total (the header's last field) and the
+// stream size, or 0 there if a bounded wait of this compression gave up.
+// (Every tile's wait ends once all tiles before it have published, which the
+// last tile's own wait has seen, so no wait can give up after this.)
+__device__ __forceinline__ void finish_stream(const FieldC& f, uint64_t mid_off, uint64_t mid_total) {
+  reinterpret_cast<uint64_t*>(f.out)[11] = mid_total;
+  const uint32_t err = __hip_atomic_load(&f.ctr->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  *f.out_size = err ? 0 : mid_off + mid_total;
+}
+
 // -------------------------------------------------------------- classify ---
 
 // mu and the constant test of every block, the state bits, and the rank of the
@@ -341,7 +453,7 @@ __device__ __forceinline__ uint32_t plan_byte(const BlockPlan<T>& p) {
 // CLS blocks, four per thread at most). The last tile writes n_nc.
 template <typename T, int B>
 __device__ __forceinline__ void classify_tile(const FieldC& f, uint32_t t, uint32_t* s_scan, uint32_t* s_state,
-                                              uint64_t* s_base) {
+                                              uint64_t* s_base, uint64_t* s_red) {
   using U = typename Traits<T>::U;
   using G = Geo<T, B>;
   constexpr int TBLK = G::TBLK;
@@ -373,13 +485,18 @@ __device__ __forceinline__ void classify_tile(const FieldC& f, uint32_t t, uint3
       kmax[i] = k < nblk ? stats[2 * k + 1] : (U)0;
     }
   }
-  const uint64_t e_bits = bound_bits(f);
+  const bool clean = *f.clean == kCleanWord;
+  for (int i = threadIdx.x; i < CLS / 32; i += kWG) s_state[i] = 0;
+  const uint64_t nchunks = cdiv(cdiv(f.n, (uint64_t)Geo<T, B>::TILE), (uint64_t)kStatsChunk);
+  const uint64_t e_bits = field_bound(f, t, clean, nchunks, s_red);
+  __syncthreads();
   const T e = from_bits<T>((U)e_bits);
-  if (t == 0 && threadIdx.x == 0) f.ctr->e_bits = e_bits;  // read by the encode pass and the header
+  if (t == 0 && threadIdx.x == 0) {
+    f.ctr->e_bits = e_bits;  // read by the encode pass
+    *f.out_size = kSizePending;
+  }
   const uint32_t ntiles = (uint32_t)cdiv(nblk, CLS);
   T* mus = reinterpret_cast<T*>(f.out + f.mu_off);
-  for (int i = threadIdx.x; i < CLS / 32; i += kWG) s_state[i] = 0;
-  __syncthreads();
   uint32_t cnt = 0, bits = 0;
   T mv[BPT];
   uint32_t pv = 0;  // plan bytes, block i in byte i
@@ -428,7 +545,18 @@ __device__ __forceinline__ void classify_tile(const FieldC& f, uint32_t t, uint3
   const uint64_t base = *s_base;
   // first rank of every encode tile that starts in this thread's blocks
   if ((k0 % TBLK) == 0 && k0 < nblk) f.enc_r0[k0 / TBLK] = base + ex;
-  if (t == ntiles - 1 && threadIdx.x == 0) f.ctr->n_nc = base + total;
+  if (t == ntiles - 1) {
+    // Every tile has published, so every tile has read the range slots: the
+    // last one clears them for the next call and marks them clean; it also
+    // writes the header (the encode pass adds the mid-byte total) and the
+    // padding between the sections.
+    const uint64_t n_nc = base + total;
+    if (threadIdx.x == 0) f.ctr->n_nc = n_nc;
+    if (threadIdx.x < kRangeSlots)
+      *reinterpret_cast<ulonglong2*>(f.range + threadIdx.x * (kRangeStride / 8)) = make_ulonglong2(0, 0);
+    if (threadIdx.x == 0) *f.clean = kCleanWord;
+    write_stream_header(f, e_bits, n_nc, 0);
+  }
 }
 
 template <typename T, int B>
@@ -437,9 +565,10 @@ __global__ __launch_bounds__(256) void k_classify(CBatch b) {
   __shared__ uint32_t s_scan[kWavesPerWG];
   __shared__ uint32_t s_state[CLS / 32 > 32 ? CLS / 32 : 32];
   __shared__ uint64_t s_base;
+  __shared__ uint64_t s_red[2 * kWavesPerWG];
   const uint64_t g = blockIdx.x;
   const FieldC f = field_at(b, field_of(b.field_cls[Traits<T>::BYTES / 8], g));
-  classify_tile<T, B>(f, (uint32_t)(g - f.base_cls), s_scan, s_state, &s_base);
+  classify_tile<T, B>(f, (uint32_t)(g - f.base_cls), s_scan, s_state, &s_base, s_red);
 }
 
 // ---------------------------------------------------------------- encode ---
@@ -667,7 +796,7 @@ __device__ __forceinline__ void tile_load(TileIn<T, B>& in, uint32_t t, const T*
 // of this type in order.
 template <typename T, int B, int BATCH>
 __device__ __forceinline__ void encode_pass(const CBatch& b, uint32_t* s_scan, uint32_t* s_tile, uint64_t* s_base,
-                                            uint32_t* s_stage) {
+                                            uint64_t* s_end, uint32_t* s_stage) {
   using U = typename Traits<T>::U;
   using G = Geo<T, B>;
   constexpr int EPL = G::EPL, LPB = G::LPB, SUB = G::SUB;
@@ -704,6 +833,10 @@ __device__ __forceinline__ void encode_pass(const CBatch& b, uint32_t* s_scan, u
   if (gt >= ntiles) return;
   TileIn<T, B> cur;
   load(cur, gt);
+  // a single call's last tile leaves its stream end to after the loop, where
+  // nothing else is live (written in the loop, it made the loop spill); the
+  // mid-byte total waits in LDS
+  if (threadIdx.x == 0) *s_end = ~0ull;
 
   for (;;) {
     const FieldC f = field_at<BATCH>(b, cur.field);
@@ -843,11 +976,26 @@ __device__ __forceinline__ void encode_pass(const CBatch& b, uint32_t* s_scan, u
     __syncthreads();
     const uint64_t base = *s_base;
     copy_out(fc.out, sec.mid + base, s_stage, tile_bytes);
-    if (t_cur == cdiv(fc.nblk, G::TBLK) - 1 && threadIdx.x == 0) fc.ctr->mid_total = base + tile_bytes;
+    if (t_cur == cdiv(fc.nblk, G::TBLK) - 1) {
+      // the field's last tile ends the mid section: its total (the last
+      // header field) and the stream size
+      if (threadIdx.x == 0) {
+        if constexpr (BATCH == kSingle)
+          *s_end = base + tile_bytes;
+        else
+          fc.ctr->mid_total = base + tile_bytes;  // for the finishing pass
+      }
+    }
     __syncthreads();
     for (int i = threadIdx.x; i < STAGE_WORDS / 4; i += kWG)
       reinterpret_cast<uint4*>(s_stage)[i] = make_uint4(0, 0, 0, 0);
     if (!more) break;
+  }
+  if constexpr (BATCH == kSingle) {
+    if (threadIdx.x == 0 && *s_end != ~0ull) {
+      const FieldC f = field_at<BATCH>(b, 0);
+      finish_stream(f, sections(f.nblk, f.ctr->n_nc, BYTES, B, 0).mid, *s_end);
+    }
   }
 }
 
@@ -857,47 +1005,32 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Geo<T, B>::
   using G = Geo<T, B>;
   __shared__ uint32_t s_scan[G::SUB * kWavesPerWG];
   __shared__ uint32_t s_tile;
-  __shared__ uint64_t s_base;
+  __shared__ uint64_t s_base, s_end;
   __shared__ __align__(16) uint32_t s_stage[(G::TILE * G::SUB * Traits<T>::BYTES + 16) / 4 + 8];
-  encode_pass<T, B, BATCH>(b, s_scan, &s_tile, &s_base, s_stage);
+  encode_pass<T, B, BATCH>(b, s_scan, &s_tile, &s_base, &s_end, s_stage);
 }
 
 // --------------------------------------------------------------- finalize ---
 
-// Header, section padding and stream size; one workgroup a field.
+// The finishing pass of a batch, one workgroup a field (a single call
+// finishes its stream in the encode pass and needs this pass only when it has
+// no values): a field with values gets its mid-byte total and stream size;
+// a field without values has no extrema, classification or encode tiles and
+// gets its whole header (the bound from an empty range) and size.
 __global__ void k_finalize(CBatch b) {
   const FieldC f = field_at(b, blockIdx.x);
-  const Counters* ctr = f.ctr;
-  // classification stores the bound (its first tile); a field without
-  // blocks has no classification tile and folds the range itself
-  const uint64_t e_bits = f.nblk ? ctr->e_bits : bound_bits(f);
-  const uint32_t w = f.dtype == 0 ? 4 : 8;
-  const uint64_t n_nc = ctr->n_nc, mid_total = ctr->mid_total;
-  const Sections s = sections(f.nblk, n_nc, w, f.b, mid_total);
-  uint8_t* out = f.out;
-  if (threadIdx.x == 0) {
-    uint32_t* o32 = reinterpret_cast<uint32_t*>(out);
-    uint64_t* o64 = reinterpret_cast<uint64_t*>(out);
-    o32[0] = kMagic;
-    o32[1] = (uint32_t)kVersion | (f.dtype << 8) | (f.eb_mode << 16) | (f.ndims << 24);
-    o32[2] = f.b;
-    o32[3] = 0;
-    for (int d = 0; d < 4; ++d) o64[2 + d] = f.dims[d];
-    o64[6] = f.n;
-    o64[7] = (uint64_t)__double_as_longlong(f.eb);
-    o64[8] = e_bits;
-    o64[9] = f.nblk;
-    o64[10] = n_nc;
-    o64[11] = mid_total;
-    *f.out_size = ctr->err ? 0 : s.total;
+  if (f.nblk != 0) {
+    if (threadIdx.x == 0) {
+      const uint32_t w = f.dtype == 0 ? 4 : 8;
+      finish_stream(f, sections(f.nblk, f.ctr->n_nc, w, f.b, 0).mid, f.ctr->mid_total);
+    }
+    return;
   }
-  // zero padding: after the state bits, after mu, after K, after codes
-  const uint64_t pads[4][2] = {{96 + cdiv(f.nblk, 8), s.mu},
-                               {s.mu + f.nblk * w, s.kbytes},
-                               {s.kbytes + n_nc, s.codes},
-                               {s.codes + n_nc * (f.b / 4), s.mid}};
-  for (int p = 0; p < 4; ++p)
-    for (uint64_t i = pads[p][0] + threadIdx.x; i < pads[p][1]; i += blockDim.x) out[i] = 0;
+  const int rel = f.eb_mode == 1;
+  const uint64_t e_bits = f.dtype == 0 ? (uint64_t)bits_of(bound_from<float>(rel, f.eb, ~0ull, 0ull))
+                                       : (uint64_t)bits_of(bound_from<double>(rel, f.eb, ~0ull, 0ull));
+  const uint64_t total = write_stream_header(f, e_bits, 0, 0);
+  if (threadIdx.x == 0) *f.out_size = total;
 }
 
 // ---------------------------------------------------------------- launch ---
@@ -909,8 +1042,6 @@ hipError_t launch_compress_b(const CBatch& b, const CLaunchGeom& g, hipStream_t 
     fn();
     if (hook) hook(name, stream, 0);
   };
-  const uint32_t gi = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(cdiv(b.zero_words, 256), 1024));
-  run("k_init", [&] { k_init<<<gi, 256, 0, stream>>>(b); });
   if (b.tiles_stats[0] + b.tiles_stats[1] > 0) {
     if (b.tiles_stats[0]) run("k_stats", [&] { k_stats<float, B><<<(uint32_t)b.tiles_stats[0], 256, 0, stream>>>(b); });
     if (b.tiles_stats[1]) run("k_stats", [&] { k_stats<double, B><<<(uint32_t)b.tiles_stats[1], 256, 0, stream>>>(b); });
@@ -933,7 +1064,8 @@ hipError_t launch_compress_b(const CBatch& b, const CLaunchGeom& g, hipStream_t 
         run("k_encode", [&] { k_encode<double, B, kBatch><<<genc, 256, 0, stream>>>(b); });
     }
   }
-  run("k_finalize", [&] { k_finalize<<<b.nfields, 64, 0, stream>>>(b); });
+  // batches finish their streams here; a single call only without values
+  if (b.fields != nullptr || b.any_empty) run("k_finalize", [&] { k_finalize<<<b.nfields, 64, 0, stream>>>(b); });
   return hipGetLastError();
 }
 

@@ -22,7 +22,9 @@ struct FieldC {
   uint32_t dtype, eb_mode, ndims, b;
   uint32_t nslots, pad;
   Counters* ctr;
+  uint64_t* clean;      // the clean word (kCleanWord: the range slots are all zero)
   uint64_t* range;      // range slots: slot i at range + i * kRangeStride / 8 (lo_inv, hi)
+  uint64_t* parts;      // first use only: per chunk, lowest and highest totalOrder key of its finite values
   void* stats;          // two totalOrder keys per block
   uint8_t* plan;        // one plan byte per block (classification -> encode)
   uint64_t* enc_r0;     // first rank of every encode tile
@@ -44,9 +46,10 @@ struct CBatch {
   uint64_t tiles_cls[2];
   uint64_t tiles_enc[2];
   uint32_t* tickets;             // 2 * kTicketClasses counters, 256 bytes apart
-  uint64_t* zero_begin;          // words cleared before each call
+  uint64_t* zero_begin;          // words the extrema pass clears (counters, tickets, status words)
   uint64_t zero_words;
-  uint32_t nfields, pad;
+  uint32_t nfields;
+  uint32_t any_empty;            // some field has no values (its header needs a pass of its own)
   FieldC one;
 };
 

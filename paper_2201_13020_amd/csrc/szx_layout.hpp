@@ -28,15 +28,26 @@ __host__ __device__ inline Sections sections(uint64_t nblk, uint64_t n_nc, uint6
   return s;
 }
 
-// Device-side counters at the start of the workspace (256 bytes reserved).
+// Device-side counters of a field's compression (256 bytes reserved; the
+// extrema pass clears them at the start of every call).
 struct Counters {
   uint32_t err;        // nonzero: a bounded wait of the compression gave up
-  uint32_t reserved[3];
+  uint32_t e_ready;    // first-use path: the bound is published in e_bits
+  uint32_t reserved[2];
   uint64_t reserved2[2];
   uint64_t n_nc;       // non-constant blocks (raw included)
-  uint64_t mid_total;  // mid-byte section size
+  uint64_t mid_total;  // mid-byte section size (batches: for the finishing pass)
   uint64_t e_bits;     // bit pattern of the bound e in the element type
 };
+
+// The range slots of a field are left all zero by every compression that
+// used them (its last classification tile clears them), which then sets the
+// field's clean word to kCleanWord. A compression that finds another value
+// there (a workspace used for the first time) does not use the slots: its
+// extrema workgroups leave one partial range per chunk instead, its first
+// classification tile folds them and publishes the bound, and its last one
+// clears the slots and sets the word.
+constexpr uint64_t kCleanWord = 0x534c4f5453303030ull;  // "000STOLS"
 
 // Validated parameters of one call.
 struct Job {
@@ -81,22 +92,26 @@ constexpr uint32_t kStatsChunk = 2;
 
 // The extrema pass folds each chunk's finite range into one of a field's
 // range slots (chunk c into slot c mod slots), by 64-bit atomic maxima of
-// the complemented smallest key and of the largest key, so that a cleared
-// slot is the identity. Device-scope atomics on one address serialise
-// (tens of ns each across XCDs), so the slots sit kRangeStride bytes apart;
-// readers fold at most kRangeSlots slots, one per lane of a wave.
+// the complemented smallest key and of the largest key, so that a zero slot
+// is the identity. Device-scope atomics on one address serialise (tens of
+// ns each across XCDs), so the slots sit kRangeStride bytes apart; readers
+// fold at most kRangeSlots slots, one per lane of a wave.
 constexpr uint32_t kRangeSlots = 64;
 constexpr uint32_t kRangeStride = 256;
 __host__ __device__ inline uint32_t range_slots(uint64_t chunks) {
   return (uint32_t)(chunks < kRangeSlots ? (chunks ? chunks : 1) : kRangeSlots);
 }
+// Bytes of a field's clean word (one line) and range slots; the same for
+// every field size, so that a workspace reused for another size finds them
+// where the last compression left them.
+constexpr uint64_t kSlotRegionBytes = 256 + (uint64_t)kRangeSlots * kRangeStride;
 
 // Values per row of a tile for block size b (mirrors Geo::TILE).
 __host__ __device__ inline uint64_t row_values(uint32_t b) { return 256ull * (b >= 512 ? b / 64 : 8); }
 
 // Per-field sizes of the passes.
 struct FieldTiles {
-  uint64_t chunks;  // extrema pass
+  uint64_t chunks;  // extrema pass (one workgroup a chunk)
   uint64_t cls;     // classification / decoder index tiles
   uint64_t enc;     // encode tiles
   uint64_t dec;     // decode tiles
@@ -111,25 +126,30 @@ __host__ __device__ inline FieldTiles field_tiles(uint64_t n, uint64_t nblk, uin
   return t;
 }
 
-// Workspace of one field: a cleared region first (counters, tickets, scan
-// status words), then the rest; every piece 256-byte aligned.
+// Workspace of one field: the clean word and range slots (at the same
+// offsets for every field size), then the region that the compression's
+// extrema pass (and the decompression's first pass) clears first --
+// counters, tickets, scan status words -- then the rest; every piece
+// 256-byte aligned.
 struct WsLayout {
-  uint64_t counters, range, tickets, cls_status, enc_mid, dec_rank, dec_mid, zero_end;
-  uint64_t stats, plan, enc_r0, dec_index, total;
+  uint64_t clean, range, counters, tickets, cls_status, enc_mid, dec_rank, dec_mid, zero_end;
+  uint64_t parts, stats, plan, enc_r0, dec_index, total;
 };
 
 __host__ __device__ inline WsLayout ws_layout(uint64_t n, uint64_t nblk, uint32_t w, uint32_t b) {
   const FieldTiles ft = field_tiles(n, nblk, w, b);
   WsLayout L;
-  L.counters = 0;
+  L.clean = 0;
   L.range = 256;
-  L.tickets = L.range + (uint64_t)range_slots(ft.chunks) * kRangeStride;
+  L.counters = kSlotRegionBytes;
+  L.tickets = L.counters + 256;
   L.cls_status = align256(L.tickets + 2ull * kTicketClasses * 256);
   L.enc_mid = align256(L.cls_status + (ft.cls + 1) * 8);
   L.dec_rank = align256(L.enc_mid + (ft.enc + 1) * 8);
   L.dec_mid = align256(L.dec_rank + (ft.cls + 1) * 8);
   L.zero_end = align256(L.dec_mid + (ft.cls + 1) * 8);
-  L.stats = L.zero_end;
+  L.parts = L.zero_end;
+  L.stats = align256(L.parts + ft.chunks * 16);
   L.plan = align256(L.stats + nblk * 2 * (uint64_t)w);
   L.enc_r0 = align256(L.plan + nblk);
   L.dec_index = align256(L.enc_r0 + (ft.enc + 1) * 8);
