@@ -317,10 +317,21 @@ __device__ __forceinline__ uint64_t field_bound(const FieldC& f, uint32_t t, boo
   }
   if (t == 0) {
     uint64_t lo = ~0ull, hi = 0;
-    for (uint64_t i = threadIdx.x; i < nchunks; i += kWG) {
-      const ulonglong2 p = reinterpret_cast<const ulonglong2*>(f.parts)[i];
-      lo = p.x < lo ? p.x : lo;
-      hi = p.y > hi ? p.y : hi;
+    // eight partials in flight per thread
+    constexpr int U = 8;
+    const ulonglong2* parts = reinterpret_cast<const ulonglong2*>(f.parts);
+    for (uint64_t i0 = 0; i0 < nchunks; i0 += (uint64_t)U * kWG) {
+      ulonglong2 p[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint64_t i = i0 + (uint64_t)u * kWG + threadIdx.x;
+        p[u] = i < nchunks ? parts[i] : make_ulonglong2(~0ull, 0ull);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        lo = p[u].x < lo ? p[u].x : lo;
+        hi = p[u].y > hi ? p[u].y : hi;
+      }
     }
     lo = group_min<kWave, uint64_t>(lo);
     hi = group_max<kWave, uint64_t>(hi);
@@ -342,14 +353,17 @@ __device__ __forceinline__ uint64_t field_bound(const FieldC& f, uint32_t t, boo
     }
     return e_bits;
   }
+  // relaxed polls (an acquiring load would invalidate caches at every poll),
+  // one acquire fence once the flag is up
   uint32_t spins = 0;
-  while (__hip_atomic_load(&f.ctr->e_ready, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+  while (__hip_atomic_load(&f.ctr->e_ready, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
     if (++spins > kSpinLimit) {
       if (l == 0) atomicMax(&f.ctr->err, 1u);
       return 0;
     }
-    __builtin_amdgcn_s_sleep(2);
+    __builtin_amdgcn_s_sleep(8);
   }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   return __hip_atomic_load(&f.ctr->e_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -398,7 +412,7 @@ __device__ __forceinline__ BlockPlan<T> plan_block(typename Traits<T>::U kmin, t
 // when the values must be verified.
 template <typename T>
 __device__ __forceinline__ uint32_t plan_byte(const BlockPlan<T>& p) {
-  return p.K < 0 ? 0xFFu : (uint32_t)p.K | (p.verify ? 0x80u : 0u);
+  return p.K < 0 ? 0xFFu : p.K == 0 ? 0u : (uint32_t)p.K | (p.verify ? 0x80u : 0u);
 }
 
 // ---------------------------------------------------------------- header ---
@@ -633,34 +647,55 @@ struct LanePacker {
 };
 
 // Copy the staged bytes [0, total) to out + [dst, dst + total): whole aligned
-// 16-byte chunks of the destination as single stores (their bytes realigned
-// from LDS with byte funnel shifts), the shared first and last chunks byte by
-// byte.
+// 16-byte chunks of the destination as single stores, the shared first and
+// last chunks byte by byte. Chunk c of the destination starts at stage byte
+// 16 c - a (a = dst mod 16, the same for every chunk), so its bytes lie in
+// the two aligned 16-byte stage words c - 1 and c (c when a = 0): every lane
+// reads two consecutive 16-byte words (a wave reads a contiguous range: no
+// LDS bank conflicts; five strided dword reads per chunk put 64 lanes on 8
+// banks) and realigns them with byte funnel shifts by the same amount.
 __device__ __forceinline__ void copy_out(uint8_t* __restrict__ out, uint64_t dst, const uint32_t* stage,
                                          uint32_t total) {
   const uint32_t st = (uint32_t)(dst & 15u);
   uint8_t* base = out + (dst - st);
   const uint32_t end = st + total;
   const uint32_t nchunk = (end + 15) / 16;
+  const uint32_t b = (16u - st) & 15u;  // byte of the chunk's start in the first stage word read
+  const uint32_t k = b >> 2, sh = b & 3u;
+  const uint32_t back = st ? 1u : 0u;
   for (uint32_t c = threadIdx.x; c < nchunk; c += kWG) {
     const uint32_t lo = c * 16 < st ? st : c * 16;
     const uint32_t hi = c * 16 + 16 > end ? end : c * 16 + 16;
     if (lo == c * 16 && hi == c * 16 + 16) {
-      const uint32_t p = c * 16 - st;  // stage byte of the chunk's first byte
-      const uint32_t q = p >> 2, sh = p & 3u;
-      uint32_t w[5];
-#pragma unroll
-      for (int i = 0; i < 5; ++i) w[i] = stage[q + i];
+      // c >= 1 here whenever st > 0 (chunk 0 is then partial)
+      const uint4 q0 = reinterpret_cast<const uint4*>(stage)[c - back];
+      const uint4 q1 = reinterpret_cast<const uint4*>(stage)[c - back + 1];
+      const uint32_t w[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
       uint4 u;
-      u.x = __builtin_amdgcn_alignbyte(w[1], w[0], sh);
-      u.y = __builtin_amdgcn_alignbyte(w[2], w[1], sh);
-      u.z = __builtin_amdgcn_alignbyte(w[3], w[2], sh);
-      u.w = __builtin_amdgcn_alignbyte(w[4], w[3], sh);
+      // k is the same for every lane: a uniform branch picks the words
+      switch (k) {
+        case 0:
+          u = make_uint4(__builtin_amdgcn_alignbyte(w[1], w[0], sh), __builtin_amdgcn_alignbyte(w[2], w[1], sh),
+                         __builtin_amdgcn_alignbyte(w[3], w[2], sh), __builtin_amdgcn_alignbyte(w[4], w[3], sh));
+          break;
+        case 1:
+          u = make_uint4(__builtin_amdgcn_alignbyte(w[2], w[1], sh), __builtin_amdgcn_alignbyte(w[3], w[2], sh),
+                         __builtin_amdgcn_alignbyte(w[4], w[3], sh), __builtin_amdgcn_alignbyte(w[5], w[4], sh));
+          break;
+        case 2:
+          u = make_uint4(__builtin_amdgcn_alignbyte(w[3], w[2], sh), __builtin_amdgcn_alignbyte(w[4], w[3], sh),
+                         __builtin_amdgcn_alignbyte(w[5], w[4], sh), __builtin_amdgcn_alignbyte(w[6], w[5], sh));
+          break;
+        default:
+          u = make_uint4(__builtin_amdgcn_alignbyte(w[4], w[3], sh), __builtin_amdgcn_alignbyte(w[5], w[4], sh),
+                         __builtin_amdgcn_alignbyte(w[6], w[5], sh), __builtin_amdgcn_alignbyte(w[7], w[6], sh));
+          break;
+      }
       *reinterpret_cast<uint4*>(base + c * 16) = u;
     } else {
       for (uint32_t i = lo; i < hi; ++i) {
-        const uint32_t b = i - st;
-        base[i] = (uint8_t)(stage[b >> 2] >> ((b & 3u) * 8u));
+        const uint32_t bi = i - st;
+        base[i] = (uint8_t)(stage[bi >> 2] >> ((bi & 3u) * 8u));
       }
     }
   }

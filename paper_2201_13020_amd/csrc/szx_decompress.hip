@@ -555,22 +555,27 @@ __device__ __forceinline__ void decode_tile(const FieldD& a, uint32_t t, uint32_
       }
     }
     if constexpr (sizeof(T) == 8 && SUB == 1) {
-      // float64 tiles of one row: the values pass through the stage in row
-      // order (lane L holds values [L EPL, (L + 1) EPL)), so that every store
-      // of a wave covers 1 KiB without gaps and can stream past the caches
+      // float64 tiles of one row: the values pass through the stage so that
+      // every store of a wave covers 1 KiB of the row without gaps and can
+      // stream past the caches. Value i of thread L (row value L EPL + i)
+      // sits at stage slot i kWG + L: the writes of a wave fill consecutive
+      // slots (no bank conflicts; lane-major slots put 64 lanes on two banks)
       __syncthreads();  // every lane is done with the staged mid bytes
       T* sv = reinterpret_cast<T*>(s_stage);
 #pragma unroll
-      for (int i = 0; i < EPL; ++i) sv[threadIdx.x * EPL + i] = v[i];
+      for (int i = 0; i < EPL; ++i) sv[i * kWG + threadIdx.x] = v[i];
       __syncthreads();
       using v4u = unsigned int __attribute__((ext_vector_type(4)));
       for (uint32_t c = threadIdx.x; c < (uint32_t)G::TILE / 2; c += kWG) {
-        const uint32_t i0 = 2 * c;
+        const uint32_t i0 = 2 * c;  // row values i0 and i0 + 1 (EPL is even)
+        const uint32_t slot = (i0 % EPL) * kWG + i0 / EPL;
         if (i0 + 2 <= nval_t) {
-          const v4u nv = *reinterpret_cast<const v4u*>(sv + i0);
+          const uint64_t a = (uint64_t)__double_as_longlong(sv[slot]);
+          const uint64_t b = (uint64_t)__double_as_longlong(sv[slot + kWG]);
+          const v4u nv = {(uint32_t)a, (uint32_t)(a >> 32), (uint32_t)b, (uint32_t)(b >> 32)};
           __builtin_nontemporal_store(nv, reinterpret_cast<v4u*>(y_t + i0));
         } else if (i0 < nval_t) {
-          y_t[i0] = sv[i0];
+          y_t[i0] = sv[slot];
         }
       }
     } else {
