@@ -62,7 +62,8 @@ def parse():
     ap.add_argument("--profile", action="store_true",
                     help="short eager run for profilers: no CPU baseline, no instrumented pass, plus a plain 256 MiB copy whose HBM counters scale the others")
     ap.add_argument("--io-dir", type=str, default=None, help="io: directory for the stream files (default: a new temporary one)")
-    ap.add_argument("--field", type=str, default="turbulence", choices=sorted(FIELDS) + ["batch", "serve", "io"],
+    ap.add_argument("--shards", type=str, default="2,4,8", help="shard: shard counts of the state vector")
+    ap.add_argument("--field", type=str, default="turbulence", choices=sorted(FIELDS) + ["batch", "serve", "io", "shard"],
                     help="batch: the many-field batch (batched launches vs per-field calls); "
                          "serve: the serving loop (continuous batching vs serial FIFO)")
     ap.add_argument("--batch-fields", type=int, default=4096, help="batch: number of fields")
@@ -519,6 +520,8 @@ def main():
         return bench_serve(args)
     if args.field == "io":
         return bench_io(args)
+    if args.field == "shard":
+        return bench_shard(args)
     dev = torch.device("cuda:0")
     cpu_leg = not args.no_cpu_baseline and not args.profile
     head = measure_field(args.field, args, dev, cpu_leg)
@@ -904,6 +907,98 @@ def bench_serve(args):
     }
     print(json.dumps(result), flush=True)
 
+
+
+def bench_shard(args):
+    """The 2^28 float64 state vector as G contiguous block-range shards on one
+    GPU (the single-GPU share of a G-GPU run, each shard in turn): the shards'
+    ranges, each shard's compression with the whole field's bound, and the
+    stitch of the shard streams into the field's stream, against the plain
+    whole-field compression; the stitched stream is checked equal to it."""
+    import numpy as np
+    import torch
+    from paper_2201_13020_amd import synth, szx
+
+    dev = torch.device("cuda:0")
+    x_np = synth.make("state")
+    x = torch.from_numpy(x_np).to(dev)
+    n, block, eb = x.numel(), BLOCK, 1e-3
+    nbytes = n * 8
+    field = szx.make_params(torch.float64, (n,), eb, "rel", block)
+    whole, wsize = szx.compress(x, eb, "rel", block)
+    torch.cuda.synchronize()
+    wn = int(wsize.cpu().view(torch.int64).item())
+    ws_whole = torch.empty(szx.workspace_size(torch.float64, (n,), eb, "rel", block), dtype=torch.uint8, device=dev)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        b.synchronize()
+        return a.elapsed_time(b) / reps
+
+    reps = max(3, args.steps // 4)
+    t_whole = timed(lambda: szx.compress(x, eb, "rel", block, out=whole, out_size=wsize, ws=ws_whole), reps)
+    rows = {}
+    for G in [int(g) for g in args.shards.split(",")]:
+        nblk = -(-n // block)
+        edges = [0] + sorted({8 * round(i * nblk / G / 8) for i in range(1, G)} - {0, nblk}) + [nblk]
+        bounds = list(zip(edges[:-1], edges[1:]))
+        parts = [x[k0 * block:min(n, k1 * block)] for k0, k1 in bounds]
+        sps = [szx.shard_params(field, k0, k1) for k0, k1 in bounds]
+        ranges = torch.empty(2 * G, dtype=torch.float64, device=dev)
+        wss = [torch.empty(int(szx.lib().sz_workspace_size(sp_byref(sp))), dtype=torch.uint8, device=dev) for sp in sps]
+        outs = [torch.empty(int(szx.lib().sz_compress_bound(sp_byref(sp))), dtype=torch.uint8, device=dev)
+                for sp in sps]
+        sizes = [torch.zeros(1, dtype=torch.uint64, device=dev) for _ in sps]
+        st_out = torch.empty_like(whole)
+        st_size = torch.zeros(1, dtype=torch.uint64, device=dev)
+
+        def ranges_all():
+            for i, xs in enumerate(parts):
+                szx.field_range(xs, block, ws=wss[i], out=ranges[2 * i:2 * i + 2])
+
+        def compress_all():
+            for i, ((k0, k1), xs) in enumerate(zip(bounds, parts)):
+                szx.compress_shard(field, k0, k1, xs, ranges, out=outs[i], out_size=sizes[i], ws=wss[i])
+
+        def stitch_all():
+            szx.stitch(field, outs, out=st_out, out_size=st_size)
+
+        t_r = timed(ranges_all, reps)
+        t_c = timed(compress_all, reps)
+        t_s = timed(stitch_all, reps)
+        torch.cuda.synchronize()
+        sn = int(st_size.cpu().view(torch.int64).item())
+        assert sn == wn and torch.equal(st_out[:sn], whole[:wn]), f"G={G}: stitched stream differs"
+        rows[str(G)] = {"range_ms": round(t_r, 4), "compress_shards_ms": round(t_c, 4), "stitch_ms": round(t_s, 4),
+                        "per_shard_compress_ms": round(t_c / G, 4),
+                        "stitch_GBps_of_stream": round(2 * sn / t_s / 1e6, 1),
+                        "total_GBps_uncompressed": round(nbytes / (t_r + t_c + t_s) / 1e6, 1)}
+        _log(f"shard G={G}: {rows[str(G)]}")
+    result = {
+        "metric": "compress GB/s (uncompressed) of a field as shards + stitch, one GPU",
+        "value": rows[max(rows, key=int)]["total_GBps_uncompressed"],
+        "unit": "GB/s", "n_gpus": 1, "steps": reps, "warmup": 1, "higher_is_better": True, "scaling": "strong",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "2^28 float64 state vector, REL 1e-3, block 128, in G contiguous block-range shards "
+                               "compressed one after another on one GPU, then stitched; value: the largest G",
+                   "parallelism": "single GPU"},
+        "detail": {"whole_field_compress_ms": round(t_whole, 4),
+                   "whole_field_GBps": round(nbytes / t_whole / 1e6, 1), "ratio": round(nbytes / wn, 4),
+                   "shards": rows},
+    }
+    print(json.dumps(result), flush=True)
+
+
+def sp_byref(sp):
+    import ctypes
+    return ctypes.byref(sp)
 
 
 def _mount_of(path):

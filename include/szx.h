@@ -139,6 +139,58 @@ sz_status sz_compress_noalloc(const sz_params* p, const void* d_in, void* d_out,
                               uint64_t out_cap, uint64_t* d_out_size,
                               hipStream_t stream);
 
+/* ---- shards of a field ----------------------------------------------------
+   Blocks are independent (Sec. IV), so a field splits into contiguous shards
+   of whole blocks, one per GPU of a multi-GPU run; only the relative bound
+   couples them (e = eb (max - min) over the whole field, Sec. III footnote).
+   The steps, each on one shard's GPU and stream:
+     1. sz_range: the shard's finite (min, max);
+     2. gather every shard's pair (an all-gather of 16 bytes per shard);
+     3. sz_compress_shard: the shard's stream with the whole field's bound;
+     4. sz_stitch: the shard streams joined section by section into the
+        stream of the whole field, byte for byte what sz_compress writes
+        (or keep the shard streams and decode each with sz_decompress).
+   Shard k covers blocks [k0, k1) of the field; k0 and k1 are multiples of 8
+   (k1 may be the field's last block count), so that state bits fill whole
+   bytes. A shard stream is a valid stream of its own values as a 1-D field
+   (sz_shard_params gives its parameters for sz_compress_bound,
+   sz_workspace_size and sz_decompress); its bound is the whole field's. */
+#define SZ_MAX_SHARDS 64
+
+/* Parameters of the shard of blocks [k0, k1) of `field` as a 1-D field.
+   Host only. Errors: SZ_EINVAL (bad field or block range). */
+sz_status sz_shard_params(const sz_params* field, uint64_t k0, uint64_t k1, sz_params* out);
+
+/* Finite range of the N values at d_in (device): d_range[0] = min,
+   d_range[1] = max as doubles (exact for both element types), or
+   (+inf, -inf) if no value is finite. d_ws as for sz_compress with p.
+   Asynchronous on `stream`. */
+sz_status sz_range(const sz_params* p, const void* d_in, double* d_range, void* d_ws, uint64_t ws_bytes,
+                   hipStream_t stream);
+
+/* Compress the shard of blocks [k0, k1) of `field` (its values at d_in,
+   device) into d_out like sz_compress with the shard's parameters, except
+   that a relative bound takes its range from the nranges (min, max) pairs at
+   d_ranges (device doubles, e.g. every shard's sz_range) instead of the
+   shard's own values. Errors as sz_compress; SZ_EINVAL for a bad block range
+   or a relative bound without ranges. */
+sz_status sz_compress_shard(const sz_params* field, uint64_t k0, uint64_t k1, const void* d_in,
+                            const double* d_ranges, uint32_t nranges, void* d_out, uint64_t out_cap,
+                            uint64_t* d_out_size, void* d_ws, uint64_t ws_bytes, hipStream_t stream);
+
+/* Join the streams of the nshards shards of `field`, in block order
+   (d_shards: host array of device pointers, 16-byte aligned; shard_caps:
+   host array of the readable bytes of each shard buffer), into the stream of
+   the whole field at d_out (out_cap >= sz_compress_bound(field)). Writes the
+   stream size to *d_out_size (device u64), or 0 if the shards do not make up
+   the field (block counts, element type, block size or bound disagree).
+   Section i of the result is the concatenation of the shards' sections i at
+   offsets from an exclusive scan of their sizes. Asynchronous on `stream`,
+   allocation-free; the shard headers are read on the device. */
+sz_status sz_stitch(const sz_params* field, uint32_t nshards, const void* const* d_shards,
+                    const uint64_t* shard_caps, void* d_out, uint64_t out_cap, uint64_t* d_out_size,
+                    hipStream_t stream);
+
 /* ---- batches (many fields, one launch per pass) ---------------------------
    A batch compresses (or decompresses) many fields of mixed element types,
    sizes and bounds with one launch per pass over all of them: one extrema

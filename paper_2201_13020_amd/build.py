@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libszx.so")
 BUILD_DIR = os.path.join(HERE, "_build")
-SOURCES = ["szx_api.hip", "szx_compress.hip", "szx_decompress.hip", "szx_server.hip", "szx_io.hip"]
+SOURCES = ["szx_api.hip", "szx_compress.hip", "szx_decompress.hip", "szx_server.hip", "szx_io.hip", "szx_shard.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

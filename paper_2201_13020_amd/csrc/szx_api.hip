@@ -465,11 +465,24 @@ sz_status sz_compress(const sz_params* p, const void* d_in, void* d_out, uint64_
   szx::Job j;
   sz_status s = make_job(p, j);
   if (s != SZ_OK) return s;
+  return compress_single(j, d_in, d_out, out_cap, d_out_size, d_ws, ws_bytes, stream, nullptr, 0);
+}
+
+}  // extern "C"
+
+namespace szx {
+namespace host {
+
+sz_status compress_single(const Job& j, const void* d_in, void* d_out, uint64_t out_cap, uint64_t* d_out_size,
+                          void* d_ws, uint64_t ws_bytes, hipStream_t stream, const double* d_ranges,
+                          uint32_t nranges) {
   if ((!d_in && j.n) || !d_out || !d_out_size || !d_ws) return fail(SZ_EINVAL, "null buffer");
   if (!aligned16(d_in) || !aligned16(d_out) || !aligned16(d_ws))
     return fail(SZ_EINVAL, "input, output and workspace must be 16-byte aligned");
-  if (out_cap < sz_compress_bound(p)) return fail(SZ_ENOSPC, "output capacity below sz_compress_bound");
-  if (ws_bytes < sz_workspace_size(p)) return fail(SZ_ENOSPC, "workspace below sz_workspace_size");
+  if (out_cap < szx::sections(j.nblk, j.nblk, j.w, j.b, j.n * j.w).total)
+    return fail(SZ_ENOSPC, "output capacity below sz_compress_bound");
+  if (ws_bytes < szx::ws_layout(j.n, j.nblk, j.w, j.b).total)
+    return fail(SZ_ENOSPC, "workspace below sz_workspace_size");
   const int ncu = cu_count();
   if (ncu <= 0) return fail(SZ_EDEVICE, "no HIP device");
   uint8_t* ws = (uint8_t*)d_ws;
@@ -478,6 +491,8 @@ sz_status sz_compress(const sz_params* p, const void* d_in, void* d_out, uint64_
   szx::CBatch b;
   memset(&b, 0, sizeof b);
   b.one = single_field_c(j, d_in, d_out, d_out_size, ws);
+  b.one.ext_range = d_ranges;
+  b.one.next_range = nranges;
   b.tiles_stats[j.dtype] = ft.chunks;
   b.tiles_cls[j.dtype] = ft.cls;
   b.tiles_enc[j.dtype] = ft.enc;
@@ -493,7 +508,8 @@ sz_status sz_compress(const sz_params* p, const void* d_in, void* d_out, uint64_
   return SZ_OK;
 }
 
-}  // extern "C"
+}  // namespace host
+}  // namespace szx
 
 // ---- allocation-free compression ------------------------------------------
 // The workspace of sz_compress_noalloc: one array per GPU, held from the

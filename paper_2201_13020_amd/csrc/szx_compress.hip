@@ -53,6 +53,7 @@ __device__ __forceinline__ FieldC field_at(const CBatch& b, uint32_t fi) {
   f.ctr = as_global(f.ctr);
   f.clean = as_global(f.clean);
   f.range = as_global(f.range);
+  f.ext_range = as_global(f.ext_range);
   f.parts = as_global(f.parts);
   f.stats = as_global(f.stats);
   f.plan = as_global(f.plan);
@@ -108,25 +109,6 @@ __device__ __forceinline__ void load_count(const T* __restrict__ x, uint32_t i0,
   }
 #pragma unroll
   for (int i = 0; i < EPL; ++i) v[i] = i < cnt ? x[i0 + i] : (T)0;
-}
-
-template <int G, typename U>
-__device__ __forceinline__ U group_min(U v) {
-#pragma unroll
-  for (int d = 1; d < G; d <<= 1) {
-    const U o = __shfl_xor(v, d, G);
-    v = o < v ? o : v;
-  }
-  return v;
-}
-template <int G, typename U>
-__device__ __forceinline__ U group_max(U v) {
-#pragma unroll
-  for (int d = 1; d < G; d <<= 1) {
-    const U o = __shfl_xor(v, d, G);
-    v = o > v ? o : v;
-  }
-  return v;
 }
 
 // Inclusive running min (MAX = false) or max over groups of G consecutive
@@ -305,6 +287,25 @@ __device__ __forceinline__ uint64_t field_bound(const FieldC& f, uint32_t t, boo
                                                uint64_t* s_red) {
   if (f.eb_mode != 1) return bound_of(f, ~0ull, 0ull);  // absolute bound: no range needed
   const uint32_t l = lane_id();
+  if (f.next_range) {
+    // a shard of a larger field: the range of the whole field from the
+    // shards' ranges (pairs of doubles, which hold the element values exactly)
+    double lo = __builtin_inf(), hi = -__builtin_inf();
+    for (uint32_t i = l; i < f.next_range; i += kWave) {
+      const double a = f.ext_range[2 * i], c = f.ext_range[2 * i + 1];
+      lo = a < lo ? a : lo;
+      hi = c > hi ? c : hi;
+    }
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      const double a = __shfl_xor(lo, d), c = __shfl_xor(hi, d);
+      lo = a < lo ? a : lo;
+      hi = c > hi ? c : hi;
+    }
+    if (!(lo <= hi) || f.eb == 0.0) return bound_of(f, ~0ull, 0ull);  // no finite value
+    return f.dtype == 0 ? (uint64_t)bits_of(round_down_to<float>(f.eb * (hi - lo)))
+                        : (uint64_t)bits_of(round_down_to<double>(f.eb * (hi - lo)));
+  }
   if (clean) {
     uint64_t lo_inv = 0, hi = 0;
     if (l < f.nslots) {

@@ -309,6 +309,27 @@ __device__ __forceinline__ V group_incl_sum(V v) {
   return v;
 }
 
+// Minimum and maximum over groups of G consecutive lanes (all lanes of a
+// group end with the group's value).
+template <int G, typename U>
+__device__ __forceinline__ U group_min(U v) {
+#pragma unroll
+  for (int d = 1; d < G; d <<= 1) {
+    const U o = __shfl_xor(v, d, G);
+    v = o < v ? o : v;
+  }
+  return v;
+}
+template <int G, typename U>
+__device__ __forceinline__ U group_max(U v) {
+#pragma unroll
+  for (int d = 1; d < G; d <<= 1) {
+    const U o = __shfl_xor(v, d, G);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
 template <int G, typename V>
 __device__ __forceinline__ V group_sum(V v) {
 #pragma unroll

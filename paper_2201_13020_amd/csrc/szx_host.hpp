@@ -44,6 +44,17 @@ sz_status plan_compress(const sz_cfield* fs, uint32_t n, uint8_t* ws, std::vecto
 sz_status plan_decompress(const sz_dfield* fs, uint32_t n, uint8_t* ws, std::vector<uint8_t>* host, BatchPlan& P,
                           DBatch* b, uint32_t* block);
 
+// One field's compression (the body of sz_compress): argument checks on the
+// buffers, then every pass on `stream`. With nranges > 0 the relative
+// bound's range is folded from the nranges pairs (min, max) at d_ranges
+// (device doubles) instead of the field's own values.
+sz_status compress_single(const Job& j, const void* d_in, void* d_out, uint64_t out_cap, uint64_t* d_out_size,
+                          void* d_ws, uint64_t ws_bytes, hipStream_t stream, const double* d_ranges,
+                          uint32_t nranges);
+
+// Whether p is 16-byte aligned.
+bool aligned16(const void* p);
+
 // Encode geometry of a compression batch from the process-wide table, by the
 // size class of each element type's total input bytes.
 CLaunchGeom batch_geom(const sz_cfield* fs, uint32_t n, int ncu);

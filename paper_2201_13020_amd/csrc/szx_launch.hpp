@@ -20,7 +20,9 @@ struct FieldC {
   uint64_t dims[4];
   double eb;
   uint32_t dtype, eb_mode, ndims, b;
-  uint32_t nslots, pad;
+  uint32_t nslots;
+  uint32_t next_range;  // > 0: the relative bound's range comes from ext_range (shards of a larger field)
+  const double* ext_range;  // next_range pairs (min, max) of finite values, as doubles
   Counters* ctr;
   uint64_t* clean;      // the clean word (kCleanWord: the range slots are all zero)
   uint64_t* range;      // range slots: slot i at range + i * kRangeStride / 8 (lo_inv, hi)

@@ -66,6 +66,14 @@ def lib():
         L.sz_compress.restype = ctypes.c_int
         L.sz_compress_noalloc.argtypes = [P, vp, vp, u64, vp, vp]
         L.sz_compress_noalloc.restype = ctypes.c_int
+        L.sz_shard_params.argtypes = [P, u64, u64, P]
+        L.sz_shard_params.restype = ctypes.c_int
+        L.sz_range.argtypes = [P, vp, vp, vp, u64, vp]
+        L.sz_range.restype = ctypes.c_int
+        L.sz_compress_shard.argtypes = [P, u64, u64, vp, vp, ctypes.c_uint32, vp, u64, vp, vp, u64, vp]
+        L.sz_compress_shard.restype = ctypes.c_int
+        L.sz_stitch.argtypes = [P, ctypes.c_uint32, ctypes.POINTER(vp), ctypes.POINTER(u64), vp, u64, vp, vp]
+        L.sz_stitch.restype = ctypes.c_int
         L.sz_decompress.argtypes = [vp, u64, P, vp, u64, vp, vp, u64, vp]
         L.sz_decompress.restype = ctypes.c_int
         L.sz_inspect.argtypes = [vp, u64, P, ctypes.POINTER(u64)]
@@ -223,6 +231,75 @@ def compress_noalloc(x, eb, mode="rel", block=128, dims=None, out=None, out_size
     rc = lib().sz_compress_noalloc(ctypes.byref(p), _ptr(x), _ptr(out), out.numel(), _ptr(out_size),
                                    _stream_handle(stream))
     _check(rc, "sz_compress_noalloc")
+    return out, out_size
+
+
+# ------------------------------------------------------------------ shards --
+
+def shard_params(field, k0, k1):
+    """Parameters (SzParams) of the shard of blocks [k0, k1) of the field
+    `field` (an SzParams) as a 1-D field."""
+    out = SzParams()
+    _check(lib().sz_shard_params(ctypes.byref(field), int(k0), int(k1), ctypes.byref(out)), "sz_shard_params")
+    return out
+
+
+def field_range(x, block=128, ws=None, out=None, stream=None):
+    """Finite (min, max) of the device tensor x as a 2-element float64 device
+    tensor ((+inf, -inf) when nothing is finite)."""
+    p = make_params(x.dtype, (x.numel(),), 0.0, "rel", block)
+    wsz = int(lib().sz_workspace_size(ctypes.byref(p)))
+    with torch.cuda.stream(stream if stream is not None else torch.cuda.current_stream(x.device)):
+        if ws is None:
+            ws = torch.empty(max(wsz, 16), dtype=torch.uint8, device=x.device)
+        if out is None:
+            out = torch.empty(2, dtype=torch.float64, device=x.device)
+    _check(lib().sz_range(ctypes.byref(p), _ptr(x), _ptr(out), _ptr(ws), ws.numel(), _stream_handle(stream)),
+           "sz_range")
+    return out
+
+
+def compress_shard(field, k0, k1, x_shard, ranges, out=None, out_size=None, ws=None, stream=None):
+    """sz_compress_shard: the stream of blocks [k0, k1) of the field `field`
+    (SzParams), whose values are the device tensor x_shard, with the bound of
+    the whole field from `ranges` (a float64 device tensor of (min, max)
+    pairs). Returns (out, out_size) as compress() does."""
+    sp = shard_params(field, k0, k1)
+    if x_shard.numel() != sp.dims[0]:
+        raise ValueError(f"shard holds {sp.dims[0]} values, got {x_shard.numel()}")
+    cap = int(lib().sz_compress_bound(ctypes.byref(sp)))
+    wsz = int(lib().sz_workspace_size(ctypes.byref(sp)))
+    with torch.cuda.stream(stream if stream is not None else torch.cuda.current_stream(x_shard.device)):
+        if out is None:
+            out = torch.empty(cap, dtype=torch.uint8, device=x_shard.device)
+        if out_size is None:
+            out_size = torch.empty(1, dtype=torch.uint64, device=x_shard.device)
+        if ws is None:
+            ws = torch.empty(wsz, dtype=torch.uint8, device=x_shard.device)
+    nr = 0 if ranges is None else ranges.numel() // 2
+    rc = lib().sz_compress_shard(ctypes.byref(field), int(k0), int(k1), _ptr(x_shard), _ptr(ranges), nr, _ptr(out),
+                                 out.numel(), _ptr(out_size), _ptr(ws), ws.numel(), _stream_handle(stream))
+    _check(rc, "sz_compress_shard")
+    return out, out_size
+
+
+def stitch(field, shards, out=None, out_size=None, stream=None):
+    """sz_stitch: the stream of the whole field `field` (SzParams) from its
+    shard streams (uint8 device tensors, in block order). Returns (out,
+    out_size)."""
+    n = len(shards)
+    ptrs = (ctypes.c_void_p * n)(*[t.data_ptr() for t in shards])
+    caps = (ctypes.c_uint64 * n)(*[t.numel() for t in shards])
+    cap = int(lib().sz_compress_bound(ctypes.byref(field)))
+    dev = shards[0].device
+    with torch.cuda.stream(stream if stream is not None else torch.cuda.current_stream(dev)):
+        if out is None:
+            out = torch.empty(cap, dtype=torch.uint8, device=dev)
+        if out_size is None:
+            out_size = torch.empty(1, dtype=torch.uint64, device=dev)
+    rc = lib().sz_stitch(ctypes.byref(field), n, ptrs, caps, _ptr(out), out.numel(), _ptr(out_size),
+                         _stream_handle(stream))
+    _check(rc, "sz_stitch")
     return out, out_size
 
 

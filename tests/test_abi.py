@@ -146,3 +146,17 @@ def test_noalloc_size_limit_is_decided_on_the_host():
     assert b"scratch" in L.sz_last_error()
     p.block_size = 12
     assert L.sz_compress_noalloc(ctypes.byref(p), None, None, 0, None, None) == 1  # SZ_EINVAL
+
+
+def test_shard_params_and_their_checks():
+    """Shard block ranges are checked on the host: multiples of 8 blocks
+    (the field's end excepted), inside the field."""
+    from paper_2201_13020_amd import szx
+    field = szx.make_params("float32", (10, 1000), 1e-3, "rel", 128)  # 79 blocks, last one short
+    sp = szx.shard_params(field, 8, 24)
+    assert sp.ndims == 1 and sp.dims[0] == 16 * 128 and sp.block_size == 128 and sp.eb_mode == field.eb_mode
+    sp = szx.shard_params(field, 72, 79)
+    assert sp.dims[0] == 10000 - 72 * 128
+    for k0, k1 in [(4, 24), (8, 20), (8, 80), (8, 8), (16, 8)]:
+        with pytest.raises(szx.SzError):
+            szx.shard_params(field, k0, k1)
