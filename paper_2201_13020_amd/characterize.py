@@ -17,7 +17,7 @@ its streams with torch on the device).
   v = fl(x - mu), zero before each block's first value. Raw blocks store the
   same in both and are left out.
 
-Run: python -m paper_2201_13020_amd.characterize --out result.json
+Run: python -m paper_2201_13020_amd.characterize --out result.json [--markdown result.md]
 """
 import argparse
 import json
@@ -174,16 +174,58 @@ def run(small=False):
     return out
 
 
+def markdown(res):
+    """The results as markdown tables: eq. (6) overhead per field, bound and
+    block size; compression ratio and PSNR per block size; the block-range
+    CDF."""
+    lines = ["## Eq. (6) space overhead of the right shift (raw blocks left out)", "",
+             "| field | REL | " + " | ".join(f"b = {b}" for b in (8, 16, 32, 64, 128)) + " |",
+             "|---|---|" + "---|" * 5]
+    for name, rows in res["overhead"].items():
+        for eb in (1e-2, 1e-3, 1e-4):
+            cells = []
+            for b in (8, 16, 32, 64, 128):
+                r = [x for x in rows if float(x["eb"]) == eb and int(x["block"]) == b]
+                cells.append(f"{100 * r[0]['overhead']:.1f} %" if r else "-")
+            lines.append(f"| {name} | {eb:g} | " + " | ".join(cells) + " |")
+    blocks = (8, 16, 32, 64, 128, 256, 512, 1024)
+    lines += ["", "## Compression ratio / PSNR (dB) against block size (max error / e in brackets)", "",
+              "| field | REL | " + " | ".join(f"b = {b}" for b in blocks) + " |", "|---|---|" + "---|" * len(blocks)]
+    for name, rows in res["sweep"].items():
+        for eb in sorted({float(r["eb"]) for r in rows}, reverse=True):
+            cells = []
+            for b in blocks:
+                r = [x for x in rows if float(x["eb"]) == eb and int(x["block"]) == b]
+                cells.append(f"{r[0]['ratio']:.2f} / {r[0]['psnr_db']:.1f} ({r[0]['max_err_over_e']:.3f})"
+                             if r else "-")
+            lines.append(f"| {name} | {eb:g} | " + " | ".join(cells) + " |")
+    lines += ["", "## Fraction of blocks whose relative value range is at most a threshold", ""]
+    for name, cdf in res["cdf"].items():
+        thr = sorted({float(t) for col in cdf.values() for t in col})
+        lines += [f"{name}:", "", "| block | " + " | ".join(f"<= {t:g}" for t in thr) + " |",
+                  "|---|" + "---|" * len(thr)]
+        for b, col in cdf.items():
+            vals = {float(t): v for t, v in col.items()}
+            lines.append(f"| {b} | " + " | ".join(f"{vals[t]:.4f}" for t in thr) + " |")
+        lines.append("")
+    return "\n".join(lines) + "\n"
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--out", default=None)
+    ap.add_argument("--out", default=None, help="write the results as JSON")
     ap.add_argument("--small", action="store_true")
+    ap.add_argument("--from-json", default=None, help="format results written earlier instead of running")
+    ap.add_argument("--markdown", default=None, help="write the results as markdown tables")
     a = ap.parse_args()
-    res = run(a.small)
+    res = json.load(open(a.from_json)) if a.from_json else run(a.small)
     text = json.dumps(res, indent=1, default=str)
     if a.out:
         with open(a.out, "w") as f:
             f.write(text)
+    if a.markdown:
+        with open(a.markdown, "w") as f:
+            f.write(markdown(res))
     print(text)
 
 
