@@ -617,7 +617,7 @@ def bench_batch(args):
         by_dtype[sp["dtype"]] += nb
     ebs = [sp["eb"] for sp in specs]
     dims = [sp["dims"] for sp in specs]
-    tuned_from_cache = tune.apply_cache()
+    tuned_from_cache = tune.apply_cache(block=BLOCK)
 
     cb = szx.compress_batch(xs, ebs, "rel", BLOCK, dims=dims)
     tuning = None

@@ -1,13 +1,15 @@
 """Autotuner of the launch geometry of the encode pass.
 
-The geometry (persistent workgroups of the encode kernel, per element type)
-never changes the output bytes; it only trades the cost of idle workgroups
-against the latency hidden by more of them. The best value depends on the
-device and on how much data a launch covers, so it is measured per (device,
-block size, element type, size class) and cached in a JSON file
-($SZX_TUNE_CACHE, default ~/.cache/szx/tune.json). Cached entries are loaded
-into the library's process-wide table, which sz_compress and new batches
-consult.
+A single-knob tuner: the knob is the number of persistent workgroups of the
+encode kernel, per element type. It never changes the output bytes; it only
+trades the cost of idle workgroups against the latency hidden by more of
+them. The best value depends on the device and on how much data a launch
+covers, so it is measured per (device, block size, element type, size class)
+and cached in a JSON file ($SZX_TUNE_CACHE, default ~/.cache/szx/tune.json).
+apply_cache loads the entries of one device and block size into the
+library's process-wide table (per element type and size class), which
+sz_compress and new batches consult. The other launch parameters (tile bytes
+of the passes) are compile-time constants of the kernels.
 """
 import json
 import os
@@ -24,8 +26,16 @@ def cache_path():
 
 
 def device_key(device=None):
+    """"<arch>|cu<compute units>" of a torch device (index or None for the
+    current one); a string is taken as a key already."""
+    if isinstance(device, str):
+        return device
     p = torch.cuda.get_device_properties(device if device is not None else torch.cuda.current_device())
     return f"{getattr(p, 'gcnArchName', p.name)}|cu{p.multi_processor_count}"
+
+
+def _compute_units(dev_key):
+    return int(dev_key.rsplit("|cu", 1)[1])
 
 
 def _load():
@@ -49,14 +59,15 @@ def _key(dev, block, dtype, cls):
     return f"{dev}|b{block}|{dtype}|c{cls}"
 
 
-def apply_cache(device=None):
-    """Load this device's cached geometries into the library table. Returns
-    the number of entries applied."""
+def apply_cache(device=None, block=128):
+    """Load the cached geometries of this device tuned at block size `block`
+    into the library table. Returns the number of entries applied."""
     dev = device_key(device)
+    want = f"b{int(block)}"
     n = 0
     for k, v in _load().items():
         parts = k.split("|")
-        if "|".join(parts[:2]) != dev or parts[2] != "b128":
+        if len(parts) != 5 or "|".join(parts[:2]) != dev or parts[2] != want:
             continue
         szx.set_geometry(parts[3], int(parts[4][1:]), int(v["encode_wgs"]))
         n += 1
@@ -78,13 +89,18 @@ def _time(fn, reps):
     return ts[len(ts) // 2]
 
 
-def tune_batch(batch, bytes_per_dtype, block=128, reps=5, multipliers=MULTIPLIERS, store=True):
+def tune_batch(batch, bytes_per_dtype, block=128, reps=5, multipliers=MULTIPLIERS, store=True,
+               timer=None, device=None):
     """Time batch.run() over the candidate encode geometries of each element
     type present (bytes_per_dtype: {"float32": bytes, "float64": bytes}), keep
-    the fastest in the batch, the library table and the cache. Returns
+    the fastest in the batch, the library table and the cache. `block` is the
+    block size of the batch's fields (part of the cache key); `timer(fn,
+    reps)` returns the time of fn in ms (default: the median of reps runs
+    between device events); `device` is a device index or key. Returns
     {dtype: (encode_wgs, ms, {candidate: ms})}."""
-    ncu = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
-    dev = device_key()
+    dev = device_key(device)
+    ncu = _compute_units(dev)
+    timer = _time if timer is None else timer
     entries = _load() if store else {}
     result = {}
     batch.run()  # warm
@@ -94,7 +110,7 @@ def tune_batch(batch, bytes_per_dtype, block=128, reps=5, multipliers=MULTIPLIER
         times = {}
         for m in multipliers:
             batch.set_geometry(m * ncu, dtype)
-            times[m * ncu] = _time(batch.run, reps)
+            times[m * ncu] = timer(batch.run, reps)
         best = min(times, key=times.get)
         batch.set_geometry(best, dtype)
         cls = szx.size_class(nbytes)
