@@ -547,7 +547,7 @@ __device__ __forceinline__ void classify_tile(const FieldC& f, uint32_t t, uint3
   const uint32_t ex = wg_excl_sum<uint32_t>(cnt, s_scan, total);  // has barriers
   if (threadIdx.x < kWave) {
     if (threadIdx.x == 0) lookback_publish(f.cls_status, t, total);
-    const uint64_t p = lookback_resolve(f.cls_status, t, total, &f.ctr->err, 1u);
+    const uint64_t p = lookback_resolve_n(f.cls_status, t, total, &f.ctr->err, 1u, ntiles);
     if (threadIdx.x == 0) *s_base = p;
   }
   // state bytes of this tile, never past the state section
@@ -615,23 +615,24 @@ __device__ __forceinline__ bool encode_try(const T (&x)[EPL], int cnt, T mu, T e
   return ok;
 }
 
-// Appends byte strings to a lane's run of the LDS byte stream. The stream is
-// zeroed beforehand and every full dword is OR-ed in (the first and last may
-// be shared with the neighbouring lanes), so the only per-value branch is the
-// predicated store itself.
+// Appends byte strings to a lane's run of the LDS byte stream, a ring of
+// wmask + 1 dwords. The ring is zeroed beforehand and every full dword is
+// OR-ed in (the first and last may be shared with the neighbouring lanes), so
+// the only per-value branch is the predicated store itself.
 struct LanePacker {
   uint32_t* stage;
-  uint32_t d;     // dword being filled
-  uint64_t acc;   // pending bytes, the next byte of the stream in the low byte
-  uint32_t fill;  // pending bits
-  __device__ __forceinline__ LanePacker(uint32_t* st, uint32_t off)
-      : stage(st), d(off >> 2), acc(0), fill((off & 3u) * 8u) {}
+  uint32_t d;      // dword being filled (before wrapping)
+  uint64_t acc;    // pending bytes, the next byte of the stream in the low byte
+  uint32_t fill;   // pending bits
+  uint32_t wmask;  // ring dwords - 1 (a power of two less one)
+  __device__ __forceinline__ LanePacker(uint32_t* st, uint32_t off, uint32_t wm)
+      : stage(st), d(off >> 2), acc(0), fill((off & 3u) * 8u), wmask(wm) {}
   // L <= 4 bytes of sv, first byte in the low byte, bytes above L zero
   __device__ __forceinline__ void put4(uint32_t sv, int L) {
     acc |= (uint64_t)sv << fill;
     fill += 8u * (uint32_t)L;
     const bool full = fill >= 32;
-    if (full) atomicOr(stage + d, (uint32_t)acc);
+    if (full) atomicOr(stage + (d & wmask), (uint32_t)acc);
     d += full ? 1u : 0u;
     acc = full ? (acc >> 32) : acc;
     fill = full ? fill - 32u : fill;
@@ -643,20 +644,23 @@ struct LanePacker {
     put4((uint32_t)(sv >> 32), L - a);
   }
   __device__ __forceinline__ void flush() {
-    if (fill > 0) atomicOr(stage + d, (uint32_t)acc);
+    if (fill > 0) atomicOr(stage + (d & wmask), (uint32_t)acc);
   }
 };
 
-// Copy the staged bytes [0, total) to out + [dst, dst + total): whole aligned
-// 16-byte chunks of the destination as single stores, the shared first and
-// last chunks byte by byte. Chunk c of the destination starts at stage byte
-// 16 c - a (a = dst mod 16, the same for every chunk), so its bytes lie in
-// the two aligned 16-byte stage words c - 1 and c (c when a = 0): every lane
-// reads two consecutive 16-byte words (a wave reads a contiguous range: no
-// LDS bank conflicts; five strided dword reads per chunk put 64 lanes on 8
-// banks) and realigns them with byte funnel shifts by the same amount.
+// Copy total staged bytes to out + [dst, dst + total). They start at the
+// 16-byte word at16 of the LDS ring of mask16 + 1 such words (a power of two)
+// and may wrap around its end. Whole aligned 16-byte chunks of the
+// destination go out as single stores, the shared first and last chunks byte
+// by byte. Chunk c of the destination starts at staged byte 16 c - a (a = dst
+// mod 16, the same for every chunk), so its bytes lie in the two staged
+// 16-byte words c - 1 and c (c when a = 0): every lane reads two consecutive
+// 16-byte words (a wave reads a contiguous range: no LDS bank conflicts; five
+// strided dword reads per chunk put 64 lanes on 8 banks) and realigns them
+// with byte funnel shifts by the same amount.
 __device__ __forceinline__ void copy_out(uint8_t* __restrict__ out, uint64_t dst, const uint32_t* stage,
-                                         uint32_t total) {
+                                         uint32_t at16, uint32_t mask16, uint32_t total) {
+  const uint4* ring = reinterpret_cast<const uint4*>(stage);
   const uint32_t st = (uint32_t)(dst & 15u);
   uint8_t* base = out + (dst - st);
   const uint32_t end = st + total;
@@ -664,13 +668,14 @@ __device__ __forceinline__ void copy_out(uint8_t* __restrict__ out, uint64_t dst
   const uint32_t b = (16u - st) & 15u;  // byte of the chunk's start in the first stage word read
   const uint32_t k = b >> 2, sh = b & 3u;
   const uint32_t back = st ? 1u : 0u;
+  const uint32_t bmask = mask16 * 16u + 15u;
   for (uint32_t c = threadIdx.x; c < nchunk; c += kWG) {
     const uint32_t lo = c * 16 < st ? st : c * 16;
     const uint32_t hi = c * 16 + 16 > end ? end : c * 16 + 16;
     if (lo == c * 16 && hi == c * 16 + 16) {
       // c >= 1 here whenever st > 0 (chunk 0 is then partial)
-      const uint4 q0 = reinterpret_cast<const uint4*>(stage)[c - back];
-      const uint4 q1 = reinterpret_cast<const uint4*>(stage)[c - back + 1];
+      const uint4 q0 = ring[(at16 + c - back) & mask16];
+      const uint4 q1 = ring[(at16 + c - back + 1) & mask16];
       const uint32_t w[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
       uint4 u;
       // k is the same for every lane: a uniform branch picks the words
@@ -695,11 +700,18 @@ __device__ __forceinline__ void copy_out(uint8_t* __restrict__ out, uint64_t dst
       *reinterpret_cast<uint4*>(base + c * 16) = u;
     } else {
       for (uint32_t i = lo; i < hi; ++i) {
-        const uint32_t bi = i - st;
+        const uint32_t bi = (at16 * 16u + i - st) & bmask;
         base[i] = (uint8_t)(stage[bi >> 2] >> ((bi & 3u) * 8u));
       }
     }
   }
+}
+
+// Clear the ring's 16-byte words that hold total bytes from word at16 on.
+__device__ __forceinline__ void ring_clear(uint32_t* stage, uint32_t at16, uint32_t mask16, uint32_t total) {
+  uint4* ring = reinterpret_cast<uint4*>(stage);
+  const uint32_t nw = (total + 15) / 16;
+  for (uint32_t i = threadIdx.x; i < nw; i += kWG) ring[(at16 + i) & mask16] = make_uint4(0, 0, 0, 0);
 }
 
 // Per-row plan of a tile's blocks as one lane sees them: K (-1 raw, 0
@@ -826,10 +838,29 @@ __device__ __forceinline__ void tile_load(TileIn<T, B>& in, uint32_t t, const T*
   for (int s = 0; s < SUB; ++s) in.row.set_rank(s, rank[s] - ((lig != 0 && in.row.K(s) != 0) ? 1u : 0u));
 }
 
+// Bytes of the encoder's LDS ring: the least power of two that holds a
+// tile's worst case (every value stored whole).
+template <typename T, int B>
+constexpr uint32_t enc_ring_bytes() {
+  constexpr uint32_t worst = (uint32_t)(Geo<T, B>::TILE * Geo<T, B>::SUB * (int)sizeof(T));
+  uint32_t r = 16;
+  while (r < worst) r *= 2;
+  return r;
+}
+
 // The encode pass for the tiles of element type T: persistent workgroups take
 // tickets from the kTicketClasses counters of this type; ticket i of class c
 // is global tile kTicketClasses * i + c, global tiles running over the fields
 // of this type in order.
+//
+// A workgroup stages each tile's mid bytes in an LDS ring (a power of two of
+// at least one tile's worst case) and leaves it there, pending, while it
+// encodes its next tile behind it; only then does it resolve the pending
+// tile's offset in the mid section and copy it out. By then the tiles before
+// it have long published their sizes, so the look-back finds them without
+// waiting, and its latency overlaps the next tile's loads. When a tile's
+// bytes would reach the pending tile's, the pending one is written out first
+// (incompressible tiles: no overlap, as with one stage).
 template <typename T, int B, int BATCH>
 __device__ __forceinline__ void encode_pass(const CBatch& b, uint32_t* s_scan, uint32_t* s_tile, uint64_t* s_base,
                                             uint64_t* s_end, uint32_t* s_stage) {
@@ -837,7 +868,8 @@ __device__ __forceinline__ void encode_pass(const CBatch& b, uint32_t* s_scan, u
   using G = Geo<T, B>;
   constexpr int EPL = G::EPL, LPB = G::LPB, SUB = G::SUB;
   constexpr int BYTES = Traits<T>::BYTES;
-  constexpr int STAGE_WORDS = (G::TILE * SUB * BYTES + 16) / 4 + 8;
+  constexpr uint32_t RING = enc_ring_bytes<T, B>();
+  constexpr uint32_t MASK16 = RING / 16 - 1;
   constexpr int DT = sizeof(T) == 4 ? 0 : 1;
   const uint64_t ntiles = b.tiles_enc[DT];
   if (ntiles == 0) return;
@@ -863,8 +895,7 @@ __device__ __forceinline__ void encode_pass(const CBatch& b, uint32_t* s_scan, u
                     f.plan, f.enc_r0, f.n, f.nblk, s_scan);
   };
 
-  for (int i = threadIdx.x; i < STAGE_WORDS / 4; i += kWG)
-    reinterpret_cast<uint4*>(s_stage)[i] = make_uint4(0, 0, 0, 0);
+  for (uint32_t i = threadIdx.x; i <= MASK16; i += kWG) reinterpret_cast<uint4*>(s_stage)[i] = make_uint4(0, 0, 0, 0);
   uint64_t gt = claim();
   if (gt >= ntiles) return;
   TileIn<T, B> cur;
@@ -873,6 +904,39 @@ __device__ __forceinline__ void encode_pass(const CBatch& b, uint32_t* s_scan, u
   // nothing else is live (written in the loop, it made the loop spill); the
   // mid-byte total waits in LDS
   if (threadIdx.x == 0) *s_end = ~0ull;
+
+  // the pending tile (same in every lane): encoded into the ring from byte
+  // p_at (16-byte aligned), its offset not yet resolved
+  bool pend = false;
+  uint32_t p_tile = 0, p_field = 0, p_bytes = 0, p_at = 0;
+  uint32_t at = 0;  // ring byte of the current tile's start (16-byte aligned)
+  // Resolve the pending tile's offset, copy it out and clear its ring bytes.
+  // (The look-back reads one status word per lane a round: status loads go
+  // to the device's coherence point, and wider windows measured slower.)
+  auto flush = [&]() {
+    const FieldC fp = field_at<BATCH>(b, p_field);
+    if (threadIdx.x < kWave) {
+      const uint64_t p = lookback_resolve<1>(fp.enc_mid, p_tile, p_bytes, &fp.ctr->err, 1u);
+      if (threadIdx.x == 0) *s_base = p;
+    }
+    __syncthreads();
+    const uint64_t base = *s_base;
+    const uint64_t mid = sections(fp.nblk, fp.ctr->n_nc, BYTES, B, 0).mid;
+    copy_out(fp.out, mid + base, s_stage, p_at / 16, MASK16, p_bytes);
+    if (p_tile == cdiv(fp.nblk, G::TBLK) - 1) {
+      // the field's last tile ends the mid section: its total (the last
+      // header field) and the stream size
+      if (threadIdx.x == 0) {
+        if constexpr (BATCH == kSingle)
+          *s_end = base + p_bytes;
+        else
+          fp.ctr->mid_total = base + p_bytes;  // for the finishing pass
+      }
+    }
+    __syncthreads();
+    ring_clear(s_stage, p_at / 16, MASK16, p_bytes);
+    pend = false;
+  };
 
   for (;;) {
     const FieldC f = field_at<BATCH>(b, cur.field);
@@ -889,6 +953,10 @@ __device__ __forceinline__ void encode_pass(const CBatch& b, uint32_t* s_scan, u
     uint32_t tile_bytes = 0;
 #pragma unroll
     for (int s = 0; s < SUB; ++s) {
+      // the ring from this tile's start up to the pending tile's must hold
+      // the row at its largest (the condition is the same in every lane); the
+      // flush's barrier orders the cleared words before this row's stores
+      if (pend && tile_bytes + (uint32_t)(G::TILE * BYTES) > RING - ((p_bytes + 15u) & ~15u)) flush();
       U q[EPL];
       int K = cur.row.K(s);
       // a wave whose blocks of this row are all constant (or past the end)
@@ -976,7 +1044,7 @@ __device__ __forceinline__ void encode_pass(const CBatch& b, uint32_t* s_scan, u
       // byte_swap(q) >> 8 ci with zero bytes above it (ci <= 3 keeps the
       // shift < 32)
       if (live) {
-        LanePacker pk(s_stage, tile_bytes + ex);
+        LanePacker pk(s_stage, at + tile_bytes + ex, RING / 4 - 1);
         if (whole) {
 #pragma unroll
           for (int i = 0; i < EPL; ++i) {
@@ -997,36 +1065,23 @@ __device__ __forceinline__ void encode_pass(const CBatch& b, uint32_t* s_scan, u
       tile_bytes += rtot;
     }
     if (threadIdx.x == 0) lookback_publish(mid_status, t, tile_bytes);
-    const uint32_t t_cur = t;
     const uint32_t f_cur = cur.field;
 
-    // the next tile's loads go out while this tile's offset is resolved
+    // the next tile's loads go out while the pending tile's offset is
+    // resolved
     gt = claim();  // its barriers also order the staging before the copy-out
     const bool more = gt < ntiles;
     if (more) load(cur, gt);
-    const FieldC fc = field_at<BATCH>(b, f_cur);
-    if (threadIdx.x < kWave) {
-      const uint64_t p = lookback_resolve(fc.enc_mid, t_cur, tile_bytes, &fc.ctr->err, 1u);
-      if (threadIdx.x == 0) *s_base = p;
-    }
-    __syncthreads();
-    const uint64_t base = *s_base;
-    copy_out(fc.out, sec.mid + base, s_stage, tile_bytes);
-    if (t_cur == cdiv(fc.nblk, G::TBLK) - 1) {
-      // the field's last tile ends the mid section: its total (the last
-      // header field) and the stream size
-      if (threadIdx.x == 0) {
-        if constexpr (BATCH == kSingle)
-          *s_end = base + tile_bytes;
-        else
-          fc.ctr->mid_total = base + tile_bytes;  // for the finishing pass
-      }
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < STAGE_WORDS / 4; i += kWG)
-      reinterpret_cast<uint4*>(s_stage)[i] = make_uint4(0, 0, 0, 0);
+    if (pend) flush();
+    pend = true;
+    p_tile = t;
+    p_field = f_cur;
+    p_bytes = tile_bytes;
+    p_at = at;
+    at = (at + ((tile_bytes + 15u) & ~15u)) & (RING - 1);
     if (!more) break;
   }
+  flush();
   if constexpr (BATCH == kSingle) {
     if (threadIdx.x == 0 && *s_end != ~0ull) {
       const FieldC f = field_at<BATCH>(b, 0);
@@ -1042,7 +1097,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Geo<T, B>::
   __shared__ uint32_t s_scan[G::SUB * kWavesPerWG];
   __shared__ uint32_t s_tile;
   __shared__ uint64_t s_base, s_end;
-  __shared__ __align__(16) uint32_t s_stage[(G::TILE * G::SUB * Traits<T>::BYTES + 16) / 4 + 8];
+  __shared__ __align__(16) uint32_t s_stage[enc_ring_bytes<T, B>() / 4];
   encode_pass<T, B, BATCH>(b, s_scan, &s_tile, &s_base, &s_end, s_stage);
 }
 

@@ -285,7 +285,7 @@ __device__ __forceinline__ void dindex_tile(const FieldD& a, uint32_t t, uint32_
   const uint32_t rex = wg_excl_sum<uint32_t>(cnt, s_scan, tnc);
   if (threadIdx.x < kWave) {
     if (threadIdx.x == 0) lookback_publish(a.rank_st, t, tnc);
-    const uint64_t p = lookback_resolve(a.rank_st, t, tnc, a.status, kStatusDevice);
+    const uint64_t p = lookback_resolve_n(a.rank_st, t, tnc, a.status, kStatusDevice, ntiles);
     if (threadIdx.x == 0) s_r0 = p;
   }
   __syncthreads();
@@ -309,7 +309,7 @@ __device__ __forceinline__ void dindex_tile(const FieldD& a, uint32_t t, uint32_
   const uint32_t mex = wg_excl_sum<uint32_t>(mid, s_scan, tmid);
   if (threadIdx.x < kWave) {
     if (threadIdx.x == 0) lookback_publish(a.mid_st, t, tmid);
-    const uint64_t p = lookback_resolve(a.mid_st, t, tmid, a.status, kStatusDevice);
+    const uint64_t p = lookback_resolve_n(a.mid_st, t, tmid, a.status, kStatusDevice, ntiles);
     if (threadIdx.x == 0) s_m0 = p;
   }
   __syncthreads();

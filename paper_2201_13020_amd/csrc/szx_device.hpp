@@ -413,11 +413,15 @@ constexpr uint32_t kSpinLimit = 1u << 18;
 // other memory of the writer: relaxed device-scope atomics are enough. (An
 // acquire/release pair would add a write-back or an invalidation of the L2 of
 // the XCD at every publish and every poll.)
+// Status words live in device memory: the accesses are typed global, so that
+// a look-back compiled out of line (its pointer generic) does not poll with
+// flat instructions.
+typedef __attribute__((address_space(1))) uint64_t global_u64;
 __device__ __forceinline__ void status_store(uint64_t* p, uint64_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store((global_u64*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ uint64_t status_load(const uint64_t* p) {
-  return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load((global_u64*)const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Device-wide exclusive prefix sums over tiles (decoupled look-back). A tile
@@ -434,9 +438,9 @@ __device__ __forceinline__ void lookback_publish(uint64_t* status, uint32_t t, u
 
 // Called by all 64 lanes of one wave after lookback_publish; returns the same
 // exclusive prefix in every lane.
+template <int R = 4>  // status words per lane per round: a window of 64 R tiles
 __device__ __noinline__ uint64_t lookback_resolve(uint64_t* status, uint32_t t, uint64_t agg,
                                                   uint32_t* err, uint32_t err_code) {
-  constexpr int R = 4;  // status words per lane per round: a window of 256 tiles
   const int lane = lane_id();
   if (t == 0) return 0;
   uint64_t excl = 0;
@@ -482,6 +486,16 @@ __device__ __noinline__ uint64_t lookback_resolve(uint64_t* status, uint32_t t, 
   }
   if (lane == 0) status_store(status + t, kFlagIncl | ((excl + agg) & kValueMask));
   return excl;
+}
+
+// The look-back with its window sized to the tiles of the scan: every status
+// load is a transaction at the device's coherence point, so where many tiles
+// are in flight a window of 64 (one word per lane) costs less than fewer,
+// wider rounds; where few are, a window of 256 covers them in one round.
+__device__ __forceinline__ uint64_t lookback_resolve_n(uint64_t* status, uint32_t t, uint64_t agg, uint32_t* err,
+                                                       uint32_t err_code, uint64_t ntiles) {
+  return ntiles > 512 ? lookback_resolve<1>(status, t, agg, err, err_code)
+                      : lookback_resolve<4>(status, t, agg, err, err_code);
 }
 
 }  // namespace szx
