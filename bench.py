@@ -558,11 +558,20 @@ def main():
         if args.field == "turbulence" and not args.no_state:
             # the 2 GiB float64 field, timed in the same run (graph replay)
             st = measure_field("state", args, dev, False)
+            sk = st["kernels"]
+            sdom = max((k for k in sk if sk[k]["alg_bytes_per_launch"]),
+                       key=lambda k: sk[k]["avg_us"] * sk[k]["launches"])
             result["detail"]["state_2p28_float64"] = {
                 "workload": f"{st['desc']}, REL {', '.join(map(str, st['bounds']))}, block {BLOCK}",
                 "round_trip_GBps": round(st["value"], 2), "ms_per_step": round(st["ms_per_step"], 4),
                 "launch": st["launch"], "input_copies": st["copies"],
-                "per_bound": st["per_bound"], "kernels": st["kernels"]}
+                "per_bound": st["per_bound"], "kernels": sk,
+                "roofline": {"bound": "hbm", "kernel": sdom, "achieved": sk[sdom]["achieved_GBps"],
+                             "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                             "frac": round(sk[sdom]["achieved_GBps"] / HBM_PEAK_GBPS, 4),
+                             "traffic": recorded_traffic(sdom, "state"),
+                             "alg_bytes_per_launch": sk[sdom]["alg_bytes_per_launch"],
+                             "avg_launch_us": sk[sdom]["avg_us"]}}
     cpu = head["cpu"]
     if cpu is not None:
         single, allc = cpu["single_thread"], cpu["all_cores"]
