@@ -873,7 +873,20 @@ __device__ __forceinline__ void encode_pass(const CBatch& b, uint32_t* s_scan, u
   constexpr int DT = sizeof(T) == 4 ? 0 : 1;
   const uint64_t ntiles = b.tiles_enc[DT];
   if (ntiles == 0) return;
-  const uint32_t cls = blockIdx.x % kTicketClasses;
+  // A single call's workgroup 0 is the scan wave of the tiles' mid-byte
+  // offsets (the others wait on one status word each); a batch's tiles, of
+  // many fields, resolve their offsets by look-back.
+  if constexpr (BATCH == kSingle) {
+    if (blockIdx.x == 0) {
+      if (threadIdx.x < kWave) {
+        const FieldC f = field_at<BATCH>(b, 0);
+        scan_wave<8>(f.enc_mid, ntiles, &f.ctr->err, 1u);
+      }
+      return;
+    }
+  }
+  const uint32_t wid = BATCH == kSingle ? blockIdx.x - 1 : blockIdx.x;
+  const uint32_t cls = wid % kTicketClasses;
   uint32_t* ticket = b.tickets + (DT * kTicketClasses + cls) * 64;
   const int lig = threadIdx.x % LPB;
 
@@ -915,7 +928,9 @@ __device__ __forceinline__ void encode_pass(const CBatch& b, uint32_t* s_scan, u
   // to the device's coherence point, and wider windows measured slower.)
   auto flush = [&]() {
     const FieldC fp = field_at<BATCH>(b, p_field);
-    if (threadIdx.x < kWave) {
+    if constexpr (BATCH == kSingle) {
+      if (threadIdx.x == 0) *s_base = scan_wait(fp.enc_mid, p_tile, p_bytes, &fp.ctr->err, 1u);
+    } else if (threadIdx.x < kWave) {
       const uint64_t p = lookback_resolve<1>(fp.enc_mid, p_tile, p_bytes, &fp.ctr->err, 1u);
       if (threadIdx.x == 0) *s_base = p;
     }
@@ -1145,12 +1160,13 @@ hipError_t launch_compress_b(const CBatch& b, const CLaunchGeom& g, hipStream_t 
       const uint64_t want = std::max<uint64_t>(g.encode_wgs[dt], kTicketClasses);
       const uint32_t genc = (uint32_t)std::min<uint64_t>(b.tiles_enc[dt], want);
       const bool batch = b.fields != nullptr;
+      // a single call adds workgroup 0, its scan wave
       if (dt == 0 && !batch)
-        run("k_encode", [&] { k_encode<float, B, kSingle><<<genc, 256, 0, stream>>>(b); });
+        run("k_encode", [&] { k_encode<float, B, kSingle><<<genc + 1, 256, 0, stream>>>(b); });
       else if (dt == 0)
         run("k_encode", [&] { k_encode<float, B, kBatch><<<genc, 256, 0, stream>>>(b); });
       else if (!batch)
-        run("k_encode", [&] { k_encode<double, B, kSingle><<<genc, 256, 0, stream>>>(b); });
+        run("k_encode", [&] { k_encode<double, B, kSingle><<<genc + 1, 256, 0, stream>>>(b); });
       else
         run("k_encode", [&] { k_encode<double, B, kBatch><<<genc, 256, 0, stream>>>(b); });
     }

@@ -488,6 +488,72 @@ __device__ __noinline__ uint64_t lookback_resolve(uint64_t* status, uint32_t t, 
   return excl;
 }
 
+// Prefix sums over tiles kept by one scan wave, for a pass whose tiles are
+// many and in flight all at once: the tiles only publish their aggregates;
+// the scan wave reads them in tile order, 64 R words a round, and publishes
+// every tile's inclusive prefix as soon as all earlier tiles have published,
+// so a tile's own wait is one status word. (A decoupled look-back walks back
+// through every tile still in flight, one window per round and per tile.)
+// The scan wave waits only on tiles that running workgroups hold, and its
+// waits are bounded like the others: on exhaustion err is raised and it
+// stops, and the tiles still waiting give up on their own bounds.
+template <int R>
+__device__ __noinline__ void scan_wave(uint64_t* status, uint64_t ntiles, uint32_t* err, uint32_t err_code) {
+  const int lane = lane_id();
+  uint64_t first = 0, run = 0;
+  uint32_t spins = 0;
+  while (first < ntiles) {
+    uint64_t w[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const uint64_t j = first + (uint64_t)(k * kWave + lane);
+      w[k] = j < ntiles ? status_load(status + j) : 0ull;
+    }
+    uint64_t adv = 0;
+    bool stop = false;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      if (stop) continue;
+      // the published words from the window's start, consecutively
+      const uint64_t pub = __ballot((w[k] >> 62) != 0);
+      const int c = pub == ~0ull ? 64 : (int)__ffsll((long long)~pub) - 1;
+      const uint64_t v = lane < c ? (w[k] & kValueMask) : 0ull;
+      const uint64_t incl = run + group_incl_sum<kWave, uint64_t>(v);
+      if (lane < c) status_store(status + first + adv + lane, kFlagIncl | (incl & kValueMask));
+      run = __shfl(incl, 63);
+      adv += (uint64_t)c;
+      stop = c < 64;
+    }
+    first += adv;
+    if (adv == 0) {
+      if (++spins > kSpinLimit) {
+        if (lane == 0) atomicMax(err, err_code);
+        return;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    } else {
+      spins = 0;
+    }
+  }
+}
+
+// A tile's exclusive prefix once the scan wave has published its inclusive
+// one (one lane polls; the value is the inclusive prefix less the tile's own
+// aggregate). Bounded: on exhaustion err is raised and 0 is returned.
+__device__ __forceinline__ uint64_t scan_wait(const uint64_t* status, uint32_t t, uint64_t agg, uint32_t* err,
+                                              uint32_t err_code) {
+  uint32_t spins = 0;
+  for (;;) {
+    const uint64_t w = status_load(status + t);
+    if ((w >> 62) == 2) return ((w & kValueMask) - agg) & kValueMask;
+    if (++spins > kSpinLimit) {
+      atomicMax(err, err_code);
+      return 0;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
+
 // The look-back with its window sized to the tiles of the scan: every status
 // load is a transaction at the device's coherence point, so where many tiles
 // are in flight a window of 64 (one word per lane) costs less than fewer,
