@@ -880,7 +880,7 @@ __device__ __forceinline__ void encode_pass(const CBatch& b, uint32_t* s_scan, u
     if (blockIdx.x == 0) {
       if (threadIdx.x < kWave) {
         const FieldC f = field_at<BATCH>(b, 0);
-        scan_wave<8>(f.enc_mid, ntiles, &f.ctr->err, 1u);
+        scan_wave<16>(f.enc_mid, ntiles, &f.ctr->err, 1u);
       }
       return;
     }
