@@ -968,10 +968,11 @@ __device__ __forceinline__ void encode_pass(const CBatch& b, uint32_t* s_scan, u
     uint32_t tile_bytes = 0;
 #pragma unroll
     for (int s = 0; s < SUB; ++s) {
-      // the ring from this tile's start up to the pending tile's must hold
-      // the row at its largest (the condition is the same in every lane); the
-      // flush's barrier orders the cleared words before this row's stores
-      if (pend && tile_bytes + (uint32_t)(G::TILE * BYTES) > RING - ((p_bytes + 15u) & ~15u)) flush();
+      if constexpr (sizeof(T) == 4) {
+        // the flush's barrier orders the cleared words before this row's
+        // stores
+        if (pend && tile_bytes + (uint32_t)(G::TILE * BYTES) > RING - ((p_bytes + 15u) & ~15u)) flush();
+      }
       U q[EPL];
       int K = cur.row.K(s);
       // a wave whose blocks of this row are all constant (or past the end)
@@ -1038,6 +1039,18 @@ __device__ __forceinline__ void encode_pass(const CBatch& b, uint32_t* s_scan, u
       }
       uint32_t rtot;
       const uint32_t ex = wg_excl_sum<uint32_t>(lb, s_scan, rtot);
+      // the ring from this tile's start up to the pending tile's must hold
+      // the row (the condition is the same in every lane). For float64 rows
+      // (16 KiB) the check takes the row's own size; float32 rows check
+      // their largest size before the row, where the flush's code does not
+      // meet the row's live registers (checked here, the float32 encoder
+      // spilled).
+      if constexpr (sizeof(T) == 8) {
+        if (pend && tile_bytes + rtot > RING - ((p_bytes + 15u) & ~15u)) {
+          flush();
+          __syncthreads();  // the cleared words before this row's stores
+        }
+      }
       if (K != 0) {
         const uint64_t r = cur.r0 + cur.row.rank(s);
         const uint64_t k = (uint64_t)t * G::TBLK + (uint64_t)s * G::TB + threadIdx.x / LPB;
