@@ -116,6 +116,37 @@ def test_parity_multidim_metadata():
         assert sf.parse(ref)["dims"] == (20, 50, 50)
 
 
+def striped(n, seed, dtype):
+    """Stripes of random length (500 to 40000 values) that alternate between
+    smooth values (tiles that compress several times) and full-entropy noise
+    (tiles whose mid bytes nearly fill a tile's worst case)."""
+    r = np.random.default_rng(seed)
+    x = smooth(n, seed).astype(np.float64)
+    i, noisy = 0, bool(r.integers(0, 2))
+    while i < n:
+        ln = int(r.integers(500, 40_000))
+        if noisy:
+            x[i:i + ln] = r.uniform(-1.0, 1.0, min(ln, n - i))
+        i += ln
+        noisy = not noisy
+    return x.astype(dtype)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("eb", [1e-3, 1e-6, 1e-12])
+def test_parity_ring_pressure(dtype, eb):
+    """The encoder keeps a finished tile's mid bytes in its LDS ring while it
+    encodes the next tile; a tile whose rows would reach them writes the
+    pending tile out first, at whatever row that happens. Striped fields put
+    that point everywhere, over many tiles; the stream must equal the
+    oracle's byte for byte."""
+    n = 1_500_037 if dtype == np.float32 else 800_011
+    x = striped(n, 17, dtype)
+    ref = check_parity(x, eb, "rel", 128, "striped")
+    info = sf.parse(ref)
+    assert 0 < info["n_nc"] < info["nblk"]
+
+
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
 @pytest.mark.parametrize("block", [8, 128])
 def test_parity_ladder_and_raw_escalation(dtype, block):
