@@ -924,8 +924,10 @@ __device__ __forceinline__ void encode_pass(const CBatch& b, uint32_t* s_scan, u
   uint32_t p_tile = 0, p_field = 0, p_bytes = 0, p_at = 0;
   uint32_t at = 0;  // ring byte of the current tile's start (16-byte aligned)
   // Resolve the pending tile's offset, copy it out and clear its ring bytes.
-  // (The look-back reads one status word per lane a round: status loads go
-  // to the device's coherence point, and wider windows measured slower.)
+  // A single call's tile waits on its own status word, which the scan wave
+  // publishes; a batch's walks back by look-back, one status word per lane a
+  // round (status loads go to the device's coherence point, and wider
+  // windows measured slower).
   auto flush = [&]() {
     const FieldC fp = field_at<BATCH>(b, p_field);
     if constexpr (BATCH == kSingle) {
