@@ -961,8 +961,12 @@ __device__ __forceinline__ void encode_pass(const CBatch& b, uint32_t* s_scan, u
     const T e = cur.e;
     const Sections sec = sections(f.nblk, cur.n_nc, BYTES, B, 0);
     uint8_t* out = f.out;
-    T* mus = reinterpret_cast<T*>(out + f.mu_off);
     uint64_t* mid_status = f.enc_mid;
+    // the tile's K bytes, codes and mu values from their first (the same in
+    // every lane); rows index them with 32-bit offsets
+    uint8_t* const kb_t = out + sec.kbytes + cur.r0;
+    uint8_t* const cd_t = out + sec.codes + cur.r0 * (B / 4);
+    T* const mus_t = reinterpret_cast<T*>(out + f.mu_off) + (uint64_t)t * G::TBLK;
     // Row by row: encode with error control (K0, then one more mantissa bit,
     // then raw; every lane votes, lanes without a coded block vote yes), codes
     // and byte counts, the row's offsets, K bytes and codes, and the staged
@@ -1054,13 +1058,12 @@ __device__ __forceinline__ void encode_pass(const CBatch& b, uint32_t* s_scan, u
         }
       }
       if (K != 0) {
-        const uint64_t r = cur.r0 + cur.row.rank(s);
-        const uint64_t k = (uint64_t)t * G::TBLK + (uint64_t)s * G::TB + threadIdx.x / LPB;
+        const uint32_t r = cur.row.rank(s);  // within the tile
         if (lig == 0) {
-          out[sec.kbytes + r] = raw ? kRawK : (uint8_t)K;
-          if (coded && raw) mus[k] = (T)0;
+          kb_t[r] = raw ? kRawK : (uint8_t)K;
+          if (coded && raw) mus_t[(uint32_t)(s * G::TB) + threadIdx.x / LPB] = (T)0;
         }
-        uint8_t* cdst = out + sec.codes + r * (B / 4) + (uint64_t)lig * (EPL / 4);
+        uint8_t* cdst = cd_t + (r * (uint32_t)(B / 4) + (uint32_t)lig * (EPL / 4));
         if constexpr (EPL == 8) {
           const uint16_t wv = (uint16_t)(((codes >> 8) & 0xFFu) | ((codes & 0xFFu) << 8));
           *reinterpret_cast<uint16_t*>(cdst) = wv;
