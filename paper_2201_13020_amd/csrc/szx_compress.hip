@@ -939,7 +939,11 @@ __device__ __forceinline__ void encode_pass(const CBatch& b, uint32_t* s_scan, u
     __syncthreads();
     const uint64_t base = *s_base;
     const uint64_t mid = sections(fp.nblk, fp.ctr->n_nc, BYTES, B, 0).mid;
-    copy_out(fp.out, mid + base, s_stage, p_at / 16, MASK16, p_bytes);
+    // the output holds the worst case (every block raw; the caller's capacity
+    // is checked against it): an offset past it can only come from a failed
+    // wait, which has raised the error already
+    if (mid + base + p_bytes <= sections(fp.nblk, fp.nblk, BYTES, B, fp.n * BYTES).total)
+      copy_out(fp.out, mid + base, s_stage, p_at / 16, MASK16, p_bytes);
     if (p_tile == cdiv(fp.nblk, G::TBLK) - 1) {
       // the field's last tile ends the mid section: its total (the last
       // header field) and the stream size
