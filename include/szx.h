@@ -86,7 +86,10 @@ uint64_t sz_compress_bound(const sz_params* p);
    compression that does not find that mark takes a slower path that does
    not trust the slots, and leaves the mark for the next call. Do not write
    into those bytes between calls (overwriting the whole workspace, its first
-   bytes included, is fine). sz_decompress does not touch them. */
+   bytes included, is fine). sz_decompress keeps two words of its own there
+   (bytes 64-71 and 128-135: a call counter and the token of the last call
+   that cleared its scan status words; every call clears them, in its first
+   kernel) and touches nothing else of them. */
 #define SZ_WS_KEPT_BYTES 16640
 uint64_t sz_workspace_size(const sz_params* p);
 

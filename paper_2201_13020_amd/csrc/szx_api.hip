@@ -365,7 +365,7 @@ sz_status plan_decompress(const sz_dfield* fs, uint32_t n, uint8_t* ws, std::vec
     P.tiles[0 + jobs[i].dtype] += ft.cls;
     P.tiles[2 + jobs[i].dtype] += ft.dec;
   }
-  uint64_t off = 256;
+  uint64_t off = 256;  // line 0: the gate's epoch and go words
   P.fields_off = off;
   off = a256(off + (uint64_t)n * sizeof(szx::FieldD));
   for (int m = 0; m < 4; ++m) {
@@ -435,6 +435,7 @@ sz_status plan_decompress(const sz_dfield* fs, uint32_t n, uint8_t* ws, std::vec
   }
   b.zero_begin = (uint64_t*)(ws + P.zero_off);
   b.zero_words = (P.zero_end - P.zero_off) / 8;
+  b.gate = (uint64_t*)ws;  // the first line (zero in the image: the first run clears)
   b.nfields = n;
   *block_out = block;
   return SZ_OK;
@@ -589,6 +590,7 @@ sz_status sz_decompress(const void* d_in, uint64_t in_bytes, const sz_params* ex
   b.tiles_dec[j.dtype] = ft.dec;
   b.zero_begin = (uint64_t*)(ws + W.dec_rank);
   b.zero_words = (W.zero_end - W.dec_rank) / 8;
+  b.gate = (uint64_t*)(ws + W.clean);
   b.nfields = 1;
   const hipError_t e = szx::launch_decompress(b, j.b, stream, current_hook());
   if (e != hipSuccess) return fail(SZ_EDEVICE, std::string("launch failed: ") + hipGetErrorString(e));

@@ -42,12 +42,66 @@ __device__ __forceinline__ FieldD field_at(const DBatch& b, uint32_t fi) {
 }
 __device__ __forceinline__ uint32_t dfield_of(const uint32_t* map, uint64_t t) { return map ? map[t] : 0u; }
 
+// Only for calls without index tiles (every field empty): their status words.
 __global__ __launch_bounds__(256) void k_dinit(DBatch b) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < b.zero_words; i += stride)
-    b.zero_begin[i] = 0;
   const uint64_t nf = b.fields ? b.nfields : 1;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nf; i += stride) *field_at(b, (uint32_t)i).status = 0;
+}
+
+// ---------------------------------------------------------------- gate ---
+// The index pass's status words and every field's status word must be zero
+// before any index tile publishes or reports an error, and no launch of its
+// own clears them. Workgroup 0 of the call's first index launch (dispatched
+// first) clears them and then stores the call's token in the go word; every
+// other workgroup waits for the token before its first publish or report
+// (its stream loads are already out). The second index launch of a mixed
+// batch finds the token there and clears nothing. The token changes with
+// every call: the last decode launch advances the epoch it comes from, when
+// no index tile reads it any more.
+__device__ __forceinline__ uint64_t gate_token(const DBatch& b) {
+  return status_load(as_global(b.gate) + kGateEpochWord) ^ kGateKey;
+}
+
+__device__ __forceinline__ void gate_open(const DBatch& b, int* s_flag) {
+  uint64_t* gate = as_global(b.gate);
+  if (threadIdx.x == 0) *s_flag = status_load(gate + kGateGoWord) != gate_token(b);
+  __syncthreads();
+  if (!*s_flag) return;  // the same in every thread
+  for (uint64_t i = threadIdx.x; i < b.zero_words; i += kWG) status_store(as_global(b.zero_begin) + i, 0);
+  const uint32_t nf = b.fields ? b.nfields : 1u;
+  for (uint32_t i = threadIdx.x; i < nf; i += kWG)
+    __hip_atomic_store((__attribute__((address_space(1))) uint32_t*)field_at(b, i).status, 0u, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  // every wave's stores are performed before the barrier (a release only: an
+  // acquire would also drop this XCD's L2)
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0) status_store(gate + kGateGoWord, gate_token(b));
+}
+
+// Every workgroup but 0 waits for the token before its first publish or
+// error report. Its later reads of the cleared words are device-scope atomic
+// loads issued after the token is seen, so they need no fence (a fence here
+// would drop the XCD's L2 for every tile). Workgroup 0 opens the gate right
+// after its descriptor and header loads (a store ahead of them would keep the
+// compiler from making them scalar loads), while the others load their state
+// bits.
+__device__ __forceinline__ void gate_wait(const DBatch& b, uint32_t* status) {
+  if (blockIdx.x == 0) return;
+  if (threadIdx.x == 0) {
+    const uint64_t* go = as_global(b.gate) + kGateGoWord;
+    const uint64_t tok = gate_token(b);
+    uint32_t spins = 0;
+    while (status_load(go) != tok) {
+      if (++spins > kSpinLimit) {
+        atomicMax(status, kStatusDevice);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+  }
+  __syncthreads();
 }
 
 __device__ __forceinline__ uint64_t rd64(const uint8_t* p) { return *reinterpret_cast<const uint64_t*>(p); }
@@ -255,17 +309,20 @@ __device__ __forceinline__ uint32_t block_mid_bytes(const uint8_t* cp, uint32_t 
 // and mid bytes, each through a light single-pass prefix sum; writes the first
 // rank and first mid byte of every decode tile in it.
 template <typename T, int B>
-__device__ __forceinline__ void dindex_tile(const FieldD& a, uint32_t t, uint32_t* s_scan, uint64_t* s_r0p,
-                                            uint64_t* s_m0p) {
+__device__ __forceinline__ void dindex_tile(const DBatch& b, const FieldD& a, uint32_t t, uint32_t* s_scan,
+                                            uint64_t* s_r0p, uint64_t* s_m0p, int* s_flag) {
   using G = Geo<T, B>;  // classification tiles follow the encode geometry
   constexpr int BYTES = Traits<T>::BYTES;
   constexpr int TBLK = G::TBLK;
   constexpr int CLS = TBLK > (int)kClsMin ? TBLK : (int)kClsMin;
   constexpr int BPT = CLS / kWG;
+  static_assert(GeoD<T, B>::TBLK % BPT == 0, "every decode tile starts at some thread's first block");
   uint64_t& s_r0 = *s_r0p;
   uint64_t& s_m0 = *s_m0p;
   const StreamInfo h = read_header<BYTES, B>(a);
+  if (blockIdx.x == 0) gate_open(b, s_flag);
   if (!h.ok) {
+    gate_wait(b, a.status);
     if (t == 0 && threadIdx.x == 0) atomicMax(a.status, kStatusCorrupt);
     return;
   }
@@ -283,6 +340,7 @@ __device__ __forceinline__ void dindex_tile(const FieldD& a, uint32_t t, uint32_
   }
   uint32_t tnc;
   const uint32_t rex = wg_excl_sum<uint32_t>(cnt, s_scan, tnc);
+  gate_wait(b, a.status);
   if (threadIdx.x < kWave) {
     if (threadIdx.x == 0) lookback_publish(a.rank_st, t, tnc);
     const uint64_t p = lookback_resolve_n(a.rank_st, t, tnc, a.status, kStatusDevice, ntiles);
@@ -332,9 +390,10 @@ template <typename T, int B>
 __global__ __launch_bounds__(256) void k_dindex(DBatch b) {
   __shared__ uint32_t s_scan[kWavesPerWG];
   __shared__ uint64_t s_r0, s_m0;
+  __shared__ int s_flag;
   const uint64_t g = blockIdx.x;
   const FieldD f = field_at(b, dfield_of(b.field_idx[Traits<T>::BYTES / 8], g));
-  dindex_tile<T, B>(f, (uint32_t)(g - f.base_idx), s_scan, &s_r0, &s_m0);
+  dindex_tile<T, B>(b, f, (uint32_t)(g - f.base_idx), s_scan, &s_r0, &s_m0, &s_flag);
 }
 
 template <typename T, int B>
@@ -593,6 +652,11 @@ __global__ __launch_bounds__(256) void k_decode(DBatch b) {
   const uint64_t g = blockIdx.x;
   const FieldD f = field_at(b, dfield_of(b.field_dec[Traits<T>::BYTES / 8], g));
   decode_tile<T, B>(f, (uint32_t)(g - f.base_dec), s_scan, s_stage);
+  // the call's last decode launch advances the gate's epoch (no index tile
+  // reads it any more); at the end, so that no load comes after the atomic
+  if (g == 0 && threadIdx.x == 0 && (sizeof(T) == 8 || b.tiles_dec[1] == 0))
+    __hip_atomic_fetch_add((__attribute__((address_space(1))) uint64_t*)(as_global(b.gate) + kGateEpochWord), 1ull,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ---------------------------------------------------------------- launch ---
@@ -604,8 +668,13 @@ hipError_t launch_decompress_b(const DBatch& b, hipStream_t stream, TimerHook ho
     fn();
     if (hook) hook(name, stream, 0);
   };
-  const uint32_t gi = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(cdiv(b.zero_words, 256), 1024));
-  run("k_dinit", [&] { k_dinit<<<gi, 256, 0, stream>>>(b); });
+  // the index pass clears what it needs itself (its gate); a call without
+  // index tiles only has status words to set
+  if (b.tiles_idx[0] + b.tiles_idx[1] == 0) {
+    const uint64_t nf = b.fields ? b.nfields : 1;
+    const uint32_t gi = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(cdiv(nf, 256), 1024));
+    run("k_dinit", [&] { k_dinit<<<gi, 256, 0, stream>>>(b); });
+  }
   if (b.tiles_idx[0]) run("k_dindex", [&] { k_dindex<float, B><<<(uint32_t)b.tiles_idx[0], 256, 0, stream>>>(b); });
   if (b.tiles_idx[1]) run("k_dindex", [&] { k_dindex<double, B><<<(uint32_t)b.tiles_idx[1], 256, 0, stream>>>(b); });
   if (b.tiles_dec[0]) run("k_decode", [&] { k_decode<float, B><<<(uint32_t)b.tiles_dec[0], 256, 0, stream>>>(b); });

@@ -80,8 +80,9 @@ struct DBatch {
   const uint32_t* field_idx[2];  // index tile -> field, per element type as in CBatch
   const uint32_t* field_dec[2];  // decode tile -> field
   uint64_t tiles_idx[2], tiles_dec[2];
-  uint64_t* zero_begin;
+  uint64_t* zero_begin;  // the index pass's status words (its gate clears them)
   uint64_t zero_words;
+  uint64_t* gate;        // the workspace line of the gate's epoch and go words
   uint32_t nfields, pad;
   FieldD one;
 };

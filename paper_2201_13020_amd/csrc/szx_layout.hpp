@@ -49,6 +49,17 @@ struct Counters {
 // clears the slots and sets the word.
 constexpr uint64_t kCleanWord = 0x534c4f5453303030ull;  // "000STOLS"
 
+// The decompression's gate: two words of the same first line of a workspace
+// (word 0 is the compression's clean word). The epoch word is advanced by
+// every decompression's last pass; the go word holds the token of the last
+// decompression that cleared its index pass's status words. A call's token is
+// its epoch mixed with kGateKey, so it differs from the token the go word
+// keeps from the call before, and from the bytes of an unused workspace but
+// for a chance of 2^-64.
+constexpr uint32_t kGateEpochWord = 8;  // byte 64 of the line
+constexpr uint32_t kGateGoWord = 16;    // byte 128
+constexpr uint64_t kGateKey = 0x9E3779B97F4A7C15ull;
+
 // Validated parameters of one call.
 struct Job {
   uint32_t dtype, eb_mode, ndims, b;
@@ -126,9 +137,10 @@ __host__ __device__ inline FieldTiles field_tiles(uint64_t n, uint64_t nblk, uin
   return t;
 }
 
-// Workspace of one field: the clean word and range slots (at the same
-// offsets for every field size), then the region that the compression's
-// extrema pass (and the decompression's first pass) clears first --
+// Workspace of one field: the clean word with the decompression's gate words
+// in its line, and the range slots (at the same offsets for every field
+// size), then the region that the compression's extrema pass (and the
+// decompression's gate) clears first --
 // counters, tickets, scan status words -- then the rest; every piece
 // 256-byte aligned.
 struct WsLayout {

@@ -70,3 +70,58 @@ def test_workspace_unmarked_again_after_overwrite():
         ws.fill_(fill)
         out, size = szx.compress(x, 1e-3, "rel", 128, ws=ws)
         assert np.array_equal(_stream(out, size), ref)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("fill", [0x00, 0xFF, 0x5A])
+def test_decompression_clears_its_words_every_call(fill):
+    """The index pass clears its look-back status words and the caller's
+    status word itself, at every call (no launch of its own does): stale
+    words between calls (all-ones words read as published prefixes), a
+    stale error status, and a workspace of arbitrary bytes must not change a
+    value or the status."""
+    rng = np.random.default_rng(13020 + 12)
+    walk = np.cumsum(rng.standard_normal((1 << 20) + 3)).astype(np.float64)
+    fields = [("sines 2^22 float32 REL 1e-3", synth.sines_1d(1 << 22), 1e-3),
+              ("random walk 2^20+3 float64 REL 1e-5", walk, 1e-5)]
+    for name, x_np, eb in fields:
+        ref = szref.compress(x_np, eb, "rel", 128)
+        yref = szref.decompress(ref).ravel()
+        exp = szx.inspect(ref[:96].tobytes())
+        stream = torch.from_numpy(ref).cuda()
+        tdt = torch.float32 if x_np.dtype == np.float32 else torch.float64
+        ws = torch.full((szx.workspace_size(tdt, x_np.shape, eb, "rel", 128),), fill, dtype=torch.uint8,
+                        device="cuda")
+        st = torch.full((1,), 3, dtype=torch.uint32, device="cuda")
+        for rnd in range(3):
+            print(f"[decompression gate fill {fill:#x}] round {rnd}: {name}", flush=True)
+            y, st = szx.decompress(stream, ref.size, exp, status=st, ws=ws)
+            torch.cuda.synchronize()
+            assert int(st.cpu().view(torch.int32).item()) == 0, (name, rnd)
+            assert same_bits(y.cpu().numpy(), yref), (name, rnd)
+            # everything past the gate's line dirtied again, and a stale status
+            ws[256:].fill_(0xFF if rnd % 2 == 0 else fill)
+            st.fill_(3)
+
+
+@pytest.mark.gpu
+def test_mixed_batch_decompression_clears_every_status():
+    """A batch of both element types: the first index launch clears the
+    statuses and status words of every field, the second finds its gate open;
+    stale statuses between runs come back zero."""
+    rng = np.random.default_rng(13020 + 13)
+    xs = [synth.sines_1d(200_000 + 17 * i, field=i).astype(np.float64 if i % 3 == 0 else np.float32)
+          for i in range(9)]
+    refs = [szref.compress(x, 1e-3, "rel", 128) for x in xs]
+    streams = [torch.from_numpy(r).cuda() for r in refs]
+    exps = [szx.inspect(r[:96].tobytes()) for r in refs]
+    d = szx.decompress_batch(streams, [r.size for r in refs], exps)
+    for rnd in range(3):
+        for s in d.statuses:
+            s.fill_(int(rng.integers(1, 5)))
+        d.run()
+        torch.cuda.synchronize()
+        for i, r in enumerate(refs):
+            assert int(d.statuses[i].cpu().view(torch.int32).item()) == 0, (rnd, i)
+            yref = szref.decompress(r).ravel()
+            assert same_bits(d.outs[i][: yref.size].cpu().numpy(), yref), (rnd, i)
