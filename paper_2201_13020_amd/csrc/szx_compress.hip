@@ -616,26 +616,30 @@ __device__ __forceinline__ bool encode_try(const T (&x)[EPL], int cnt, T mu, T e
 }
 
 // Appends byte strings to a lane's run of the LDS byte stream, a ring of
-// wmask + 1 dwords. The ring is zeroed beforehand and every full dword is
+// bmask + 1 bytes. The ring is zeroed beforehand and every full dword is
 // OR-ed in (the first and last may be shared with the neighbouring lanes), so
 // the only per-value branch is the predicated store itself.
 struct LanePacker {
-  uint32_t* stage;
-  uint32_t d;      // dword being filled (before wrapping)
-  uint64_t acc;    // pending bytes, the next byte of the stream in the low byte
-  uint32_t fill;   // pending bits
-  uint32_t wmask;  // ring dwords - 1 (a power of two less one)
-  __device__ __forceinline__ LanePacker(uint32_t* st, uint32_t off, uint32_t wm)
-      : stage(st), d(off >> 2), acc(0), fill((off & 3u) * 8u), wmask(wm) {}
+  uint8_t* stage;
+  uint32_t da;     // ring byte of the dword being filled (a multiple of 4)
+  uint32_t lo, hi; // pending bytes, the next byte of the stream in the low byte of lo
+  uint32_t fill;   // pending bits (< 32)
+  uint32_t bmask;  // ring bytes - 1 (a power of two less one)
+  __device__ __forceinline__ LanePacker(uint32_t* st, uint32_t off, uint32_t bm)
+      : stage(reinterpret_cast<uint8_t*>(st)), da(off & ~3u & bm), lo(0), hi(0), fill((off & 3u) * 8u), bmask(bm) {}
   // L <= 4 bytes of sv, first byte in the low byte, bytes above L zero
   __device__ __forceinline__ void put4(uint32_t sv, int L) {
-    acc |= (uint64_t)sv << fill;
-    fill += 8u * (uint32_t)L;
-    const bool full = fill >= 32;
-    if (full) atomicOr(stage + (d & wmask), (uint32_t)acc);
-    d += full ? 1u : 0u;
-    acc = full ? (acc >> 32) : acc;
-    fill = full ? fill - 32u : fill;
+    const uint64_t sh = (uint64_t)sv << fill;
+    lo |= (uint32_t)sh;
+    hi |= (uint32_t)(sh >> 32);
+    const uint32_t nf = fill + 8u * (uint32_t)L;  // < 64
+    fill = nf & 31u;
+    if (nf > 31u) {
+      atomicOr(reinterpret_cast<uint32_t*>(stage + da), lo);
+      da = (da + 4u) & bmask;
+      lo = hi;
+      hi = 0;
+    }
   }
   __device__ __forceinline__ void put(uint32_t sv, int L) { put4(sv, L); }
   __device__ __forceinline__ void put(uint64_t sv, int L) {
@@ -644,9 +648,19 @@ struct LanePacker {
     put4((uint32_t)(sv >> 32), L - a);
   }
   __device__ __forceinline__ void flush() {
-    if (fill > 0) atomicOr(stage + (d & wmask), (uint32_t)acc);
+    if (fill > 0) atomicOr(reinterpret_cast<uint32_t*>(stage + da), lo);
   }
 };
+
+// The bytes of v after its c lowest ones (c in [0, 3]; v's string after
+// dropping c leading bytes when the first byte is the low one).
+__device__ __forceinline__ uint32_t drop_low_bytes(uint32_t v, uint32_t c) {
+  return __builtin_amdgcn_alignbyte(0u, v, c);
+}
+__device__ __forceinline__ uint64_t drop_low_bytes(uint64_t v, uint32_t c) {
+  const uint32_t l = (uint32_t)v, h = (uint32_t)(v >> 32);
+  return ((uint64_t)__builtin_amdgcn_alignbyte(0u, h, c) << 32) | __builtin_amdgcn_alignbyte(h, l, c);
+}
 
 // Copy total staged bytes to out + [dst, dst + total). They start at the
 // 16-byte word at16 of the LDS ring of mask16 + 1 such words (a power of two)
@@ -1078,22 +1092,21 @@ __device__ __forceinline__ void encode_pass(const CBatch& b, uint32_t* s_scan, u
       }
       // stage the kept bytes of each value, most significant first: q holds
       // only its top nb bytes, so after the byte swap the value's string is
-      // byte_swap(q) >> 8 ci with zero bytes above it (ci <= 3 keeps the
-      // shift < 32)
+      // byte_swap(q) without its ci low bytes, zero bytes above it
       if (live) {
-        LanePacker pk(s_stage, at + tile_bytes + ex, RING / 4 - 1);
+        LanePacker pk(s_stage, at + tile_bytes + ex, RING - 1);
         if (whole) {
 #pragma unroll
           for (int i = 0; i < EPL; ++i) {
             const int ci = (int)((codes >> (2 * (EPL - 1 - i))) & 3u);
-            pk.put((U)(byte_swap(q[i]) >> (8 * ci)), nb - ci);
+            pk.put(drop_low_bytes(byte_swap(q[i]), (uint32_t)ci), nb - ci);
           }
         } else {
 #pragma unroll
           for (int i = 0; i < EPL; ++i) {
             const int ci = (int)((codes >> (2 * (EPL - 1 - i))) & 3u);
             const bool valid = i < cnt_s;
-            const U sv = valid ? (U)(byte_swap(q[i]) >> (8 * ci)) : (U)0;
+            const U sv = valid ? drop_low_bytes(byte_swap(q[i]), (uint32_t)ci) : (U)0;
             pk.put(sv, valid ? nb - ci : 0);
           }
         }
