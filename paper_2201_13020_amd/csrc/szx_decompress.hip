@@ -27,6 +27,7 @@ namespace szx {
 
 constexpr uint32_t kStatusCorrupt = 3;  // SZ_ECORRUPT
 constexpr uint32_t kStatusDevice = 4;   // SZ_EDEVICE: a bounded wait gave up
+constexpr uint32_t kDirectRankTiles = 256;  // index tiles that count their first rank directly
 
 // Field of a call, or of a batch entry (a copy with its pointers typed as
 // global memory).
@@ -338,10 +339,35 @@ __device__ __forceinline__ void dindex_tile(const DBatch& b, const FieldD& a, ui
     ncb |= (nc ? 1u : 0u) << i;
     cnt += nc ? 1u : 0u;
   }
-  uint32_t tnc;
-  const uint32_t rex = wg_excl_sum<uint32_t>(cnt, s_scan, tnc);
+  // A tile whose preceding state bits are few (the first kDirectRankTiles
+  // tiles: at most 32 KiB of them) counts its first rank directly, as the
+  // population count of those bits (16-byte words from a 16-byte aligned
+  // section, all loads issued at once), and publishes it as inclusive; later
+  // tiles chain by look-back and stop at those words.
+  const bool direct = t < kDirectRankTiles;
+  uint32_t pop = 0;
+  if (direct) {
+    constexpr uint32_t W16 = kDirectRankTiles * (CLS / 8) / 16 / kWG;  // words per thread, at most
+    const uint32_t n16 = t * (CLS / 8) / 16;
+    const uint4* sp = reinterpret_cast<const uint4*>(in + h.sec.state);
+    uint4 u[W16];
+#pragma unroll
+    for (uint32_t j = 0; j < W16; ++j) {
+      const uint32_t i = threadIdx.x + j * kWG;
+      u[j] = i < n16 ? sp[i] : make_uint4(0, 0, 0, 0);
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < W16; ++j) pop += __popc(u[j].x) + __popc(u[j].y) + __popc(u[j].z) + __popc(u[j].w);
+  }
+  const uint32_t v2[2] = {cnt, pop};
+  uint32_t ex2[2], tot2[2];
+  wg_excl_scan_multi<2>(v2, ex2, tot2, s_scan);
+  const uint32_t rex = ex2[0], tnc = tot2[0];
   gate_wait(b, a.status);
-  if (threadIdx.x < kWave) {
+  if (direct) {
+    if (threadIdx.x == 0) status_store(a.rank_st + t, kFlagIncl | (((uint64_t)tot2[1] + tnc) & kValueMask));
+    if (threadIdx.x == 0) s_r0 = tot2[1];
+  } else if (threadIdx.x < kWave) {
     if (threadIdx.x == 0) lookback_publish(a.rank_st, t, tnc);
     const uint64_t p = lookback_resolve_n(a.rank_st, t, tnc, a.status, kStatusDevice, ntiles);
     if (threadIdx.x == 0) s_r0 = p;
@@ -388,7 +414,7 @@ __device__ __forceinline__ void dindex_tile(const DBatch& b, const FieldD& a, ui
 
 template <typename T, int B>
 __global__ __launch_bounds__(256) void k_dindex(DBatch b) {
-  __shared__ uint32_t s_scan[kWavesPerWG];
+  __shared__ uint32_t s_scan[2 * kWavesPerWG];
   __shared__ uint64_t s_r0, s_m0;
   __shared__ int s_flag;
   const uint64_t g = blockIdx.x;
