@@ -61,7 +61,8 @@ typedef enum {
 } sz_status;
 
 /* Parameters of one field. Dims are metadata: blocks run over the row-major
-   flattening (Sec. IV: "many small 1D blocks"), N = dims[0]*...*dims[ndims-1]. */
+   flattening (Sec. IV splits the data into short one-dimensional blocks),
+   N = dims[0]*...*dims[ndims-1]. */
 typedef struct {
   uint32_t dtype;      /* sz_dtype */
   uint32_t ndims;      /* 1..4 */

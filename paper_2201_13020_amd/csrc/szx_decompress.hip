@@ -2,12 +2,15 @@
 //
 // Two kernels per call:
 //   k_dindex  over tiles of consecutive blocks: state bits give each tile's
-//             non-constant blocks, a light single-pass prefix count their
-//             ranks (hence their K byte and codes); per value the number of
+//             non-constant blocks and their ranks (hence their K byte and
+//             codes) -- the population count of the state bits before the
+//             tile for the first 256 tiles, a light single-pass prefix count
+//             after them; workgroup 0 first clears the status words that the
+//             prefix sums use (a gate holds the others); per value the number of
 //             stored mid bytes is the kept bytes minus the leading bytes its
 //             2-bit code shares, and a second light prefix sum gives the first
-//             mid byte of every decode tile ("a parallel prefix-scan is applied
-//             before retrieving the mid-bytes", Sec. V-B).
+//             mid byte of every decode tile (Sec. V-B locates the mid bytes by
+//             a prefix sum of these counts before they are read).
 //   k_decode  every decode tile on its own, no waiting: it stages its mid bytes
 //             in LDS with aligned 16-byte loads, resolves leading bytes -- byte
 //             j of value i is the stored byte j of the nearest value i' <= i
