@@ -642,10 +642,28 @@ struct LanePacker {
     }
   }
   __device__ __forceinline__ void put(uint32_t sv, int L) { put4(sv, L); }
+  // L <= 8 bytes of sv at once: the 96-bit window lo, hi, x takes them at
+  // bit `fill`, and up to two full dwords leave
   __device__ __forceinline__ void put(uint64_t sv, int L) {
-    const int a = L < 4 ? L : 4;
-    put4((uint32_t)sv, a);
-    put4((uint32_t)(sv >> 32), L - a);
+    const uint64_t a = (uint64_t)(uint32_t)sv << fill;
+    const uint64_t b = (sv >> 32) << fill;
+    lo |= (uint32_t)a;
+    hi |= (uint32_t)(a >> 32) | (uint32_t)b;
+    const uint32_t x = (uint32_t)(b >> 32);
+    const uint32_t nf = fill + 8u * (uint32_t)L;  // < 96
+    fill = nf & 31u;
+    if (nf > 31u) {
+      atomicOr(reinterpret_cast<uint32_t*>(stage + da), lo);
+      da = (da + 4u) & bmask;
+      lo = hi;
+      hi = x;
+      if (nf > 63u) {
+        atomicOr(reinterpret_cast<uint32_t*>(stage + da), lo);
+        da = (da + 4u) & bmask;
+        lo = hi;
+        hi = 0;
+      }
+    }
   }
   __device__ __forceinline__ void flush() {
     if (fill > 0) atomicOr(reinterpret_cast<uint32_t*>(stage + da), lo);
