@@ -252,9 +252,12 @@ __device__ __forceinline__ void stats_chunk(const FieldC& f, uint64_t c, uint64_
   }
 }
 
-// Before any work, every extrema workgroup (of both element types) clears
-// its slice of the words that the later passes count, publish and wait on:
-// they run after this pass, and nothing in it reads them.
+// Every extrema workgroup (of both element types) also clears its slice of
+// the words that the later passes count, publish and wait on: they run after
+// this pass, and nothing in it reads them. A single call and a batch take
+// separate (uniform) paths, so that each reads its descriptor with scalar
+// loads: one expression choosing between the kernel argument and the table
+// would read it through a generic pointer.
 template <typename T, int B>
 __global__ __launch_bounds__(256) void k_stats(CBatch b) {
   __shared__ uint64_t s_lo[kWavesPerWG], s_hi[kWavesPerWG];
@@ -263,8 +266,13 @@ __global__ __launch_bounds__(256) void k_stats(CBatch b) {
   const uint64_t all = b.tiles_stats[0] + b.tiles_stats[1];
   for (uint64_t i = ((DT ? b.tiles_stats[0] : 0) + g) * kWG + threadIdx.x; i < b.zero_words; i += all * kWG)
     b.zero_begin[i] = 0;
-  const FieldC f = field_at(b, field_of(b.field_stats[DT], g));
-  stats_chunk<T, B>(f, g - f.base_stats, s_lo, s_hi);
+  if (b.fields) {
+    const FieldC f = field_at<kBatch>(b, field_of<kBatch>(b.field_stats[DT], g));
+    stats_chunk<T, B>(f, g - f.base_stats, s_lo, s_hi);
+  } else {
+    const FieldC f = field_at<kSingle>(b, 0);
+    stats_chunk<T, B>(f, g, s_lo, s_hi);
+  }
 }
 
 // ----------------------------------------------------------------- range ---
