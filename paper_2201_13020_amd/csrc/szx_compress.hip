@@ -833,37 +833,67 @@ __device__ __forceinline__ void tile_load(TileIn<T, B>& in, uint32_t t, const T*
     const T* x_t = x + kb * B;
     const T* mus_t = mus + kb;
     const uint8_t* plan_t = plan + kb;
+    // every row's mu and plan byte first, then the values: vector loads
+    // return in order, so a row's plan byte read after the previous row's
+    // values would wait for them (one memory latency per row)
+    uint32_t pbs[SUB];
+#pragma unroll
+    for (int s = 0; s < SUB; ++s) {
+      const uint32_t lk = (uint32_t)(s * TB + g);
+      in.mu[s] = (T)0;
+      pbs[s] = 0;
+      if (lk < nblk_t) {
+        in.mu[s] = mus_t[lk];
+        pbs[s] = plan_t[lk];
+      }
+    }
+    // The values through a buffer resource over the tile's values (to the
+    // field's end): reads past its range return zeros without touching
+    // memory, so lanes of constant blocks (sent far past it) and a short
+    // block's run past the field's end need no branch. With one load form
+    // for every lane no lane's loads wait on another's (two forms writing
+    // the same registers made every row wait for all loads before it).
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(x_t), (short)0, (int)(nval_t * sizeof(T)), 0x00020000);
+    using v4u = unsigned int __attribute__((ext_vector_type(4)));
 #pragma unroll
     for (int s = 0; s < SUB; ++s) {
       const uint32_t lk = (uint32_t)(s * TB + g);
       const bool inb = lk < nblk_t;
-      T mu = (T)0;
-      uint32_t pb = 0;
-      if (inb) {
-        mu = mus_t[lk];
-        pb = plan_t[lk];
-      }
+      const uint32_t pb = pbs[s];
       const int K = pb == 0xFFu ? -1 : (int)(pb & 0x7Fu);
-      in.mu[s] = mu;
       // values from this lane's first one to the tile's end (constant blocks load none)
       const int rem = (int)nval_t - (int)(lk * B) - lig * EPL;
       const int cnt = (inb && K != 0) ? (rem < 0 ? 0 : (rem > EPL ? EPL : rem)) : 0;
       in.row.set(s, K, (pb & 0x80u) != 0 && pb != 0xFFu, cnt);
-      load_count<T, EPL>(x_t, lk * B + (uint32_t)(lig * EPL), cnt, in.x[s]);
+      const uint32_t off = cnt > 0 ? (lk * B + (uint32_t)(lig * EPL)) * 4u : 0x40000000u;
+#pragma unroll
+      for (int c = 0; c < EPL / 4; ++c) {
+        const v4u u = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(off + 16u * (uint32_t)c), 0, 0);
+        in.x[s][4 * c + 0] = __uint_as_float(u.x);
+        in.x[s][4 * c + 1] = __uint_as_float(u.y);
+        in.x[s][4 * c + 2] = __uint_as_float(u.z);
+        in.x[s][4 * c + 3] = __uint_as_float(u.w);
+      }
       first[s] = (lig == 0 && K != 0) ? 1u : 0u;
     }
   } else {
+    uint32_t pbs[SUB];  // as above: every row's plan byte before any value
 #pragma unroll
     for (int s = 0; s < SUB; ++s) {
       const uint64_t k = (uint64_t)t * TBLK + (uint64_t)s * TB + g;
-      T mu = (T)0;
-      uint32_t pb = 0;
+      in.mu[s] = (T)0;
+      pbs[s] = 0;
       if (k < nblk) {
-        mu = mus[k];
-        pb = plan[k];
+        in.mu[s] = mus[k];
+        pbs[s] = plan[k];
       }
+    }
+#pragma unroll
+    for (int s = 0; s < SUB; ++s) {
+      const uint64_t k = (uint64_t)t * TBLK + (uint64_t)s * TB + g;
+      const uint32_t pb = pbs[s];
       const int K = pb == 0xFFu ? -1 : (int)(pb & 0x7Fu);
-      in.mu[s] = mu;
       const uint64_t nk = (k < nblk && K != 0) ? std::min<uint64_t>((uint64_t)B, n - k * B) : 0;
       const int cnt = (int)((uint64_t)lig * EPL >= nk ? 0 : std::min<uint64_t>(EPL, nk - (uint64_t)lig * EPL));
       in.row.set(s, K, (pb & 0x80u) != 0 && pb != 0xFFu, cnt);
@@ -968,10 +998,10 @@ __device__ __forceinline__ void encode_pass(const CBatch& b, uint32_t* s_scan, u
   // publishes; a batch's walks back by look-back, one status word per lane a
   // round (status loads go to the device's coherence point, and wider
   // windows measured slower).
-  auto flush = [&]() {
+  auto flush = [&](uint64_t first_poll) {
     const FieldC fp = field_at<BATCH>(b, p_field);
     if constexpr (BATCH == kSingle) {
-      if (threadIdx.x == 0) *s_base = scan_wait(fp.enc_mid, p_tile, p_bytes, &fp.ctr->err, 1u);
+      if (threadIdx.x == 0) *s_base = scan_wait(fp.enc_mid, p_tile, p_bytes, &fp.ctr->err, 1u, first_poll);
     } else if (threadIdx.x < kWave) {
       const uint64_t p = lookback_resolve<1>(fp.enc_mid, p_tile, p_bytes, &fp.ctr->err, 1u);
       if (threadIdx.x == 0) *s_base = p;
@@ -1021,7 +1051,7 @@ __device__ __forceinline__ void encode_pass(const CBatch& b, uint32_t* s_scan, u
       if constexpr (sizeof(T) == 4) {
         // the flush's barrier orders the cleared words before this row's
         // stores
-        if (pend && tile_bytes + (uint32_t)(G::TILE * BYTES) > RING - ((p_bytes + 15u) & ~15u)) flush();
+        if (pend && tile_bytes + (uint32_t)(G::TILE * BYTES) > RING - ((p_bytes + 15u) & ~15u)) flush(0);
       }
       U q[EPL];
       int K = cur.row.K(s);
@@ -1097,7 +1127,7 @@ __device__ __forceinline__ void encode_pass(const CBatch& b, uint32_t* s_scan, u
       // spilled).
       if constexpr (sizeof(T) == 8) {
         if (pend && tile_bytes + rtot > RING - ((p_bytes + 15u) & ~15u)) {
-          flush();
+          flush(0);
           __syncthreads();  // the cleared words before this row's stores
         }
       }
@@ -1144,11 +1174,17 @@ __device__ __forceinline__ void encode_pass(const CBatch& b, uint32_t* s_scan, u
     const uint32_t f_cur = cur.field;
 
     // the next tile's loads go out while the pending tile's offset is
-    // resolved
+    // resolved. A single call reads the pending tile's offset word before
+    // them: vector loads return in order, so a read issued after the tile's
+    // loads would wait for all of them
     gt = claim();  // its barriers also order the staging before the copy-out
     const bool more = gt < ntiles;
+    uint64_t first_poll = 0;
+    if constexpr (BATCH == kSingle) {
+      if (pend && threadIdx.x == 0) first_poll = status_load(field_at<BATCH>(b, p_field).enc_mid + p_tile);
+    }
     if (more) load(cur, gt);
-    if (pend) flush();
+    if (pend) flush(first_poll);
     pend = true;
     p_tile = t;
     p_field = f_cur;
@@ -1157,7 +1193,7 @@ __device__ __forceinline__ void encode_pass(const CBatch& b, uint32_t* s_scan, u
     at = (at + ((tile_bytes + 15u) & ~15u)) & (RING - 1);
     if (!more) break;
   }
-  flush();
+  flush(0);
   if constexpr (BATCH == kSingle) {
     if (threadIdx.x == 0 && *s_end != ~0ull) {
       const FieldC f = field_at<BATCH>(b, 0);

@@ -541,7 +541,9 @@ __device__ __noinline__ void scan_wave(uint64_t* status, uint64_t ntiles, uint32
 // one (one lane polls; the value is the inclusive prefix less the tile's own
 // aggregate). Bounded: on exhaustion err is raised and 0 is returned.
 __device__ __forceinline__ uint64_t scan_wait(const uint64_t* status, uint32_t t, uint64_t agg, uint32_t* err,
-                                              uint32_t err_code) {
+                                              uint32_t err_code, uint64_t first = 0) {
+  // `first`: the word as read earlier by the caller (0: not read)
+  if ((first >> 62) == 2) return ((first & kValueMask) - agg) & kValueMask;
   uint32_t spins = 0;
   for (;;) {
     const uint64_t w = status_load(status + t);
