@@ -462,18 +462,33 @@ __device__ __forceinline__ void decode_tile(const FieldD& a, uint32_t t, uint32_
     const uint64_t left = a.in_bytes > src0 ? a.in_bytes - src0 : 0;
     const uint32_t avail = (uint32_t)std::min<uint64_t>(left, 0xFFFFFFFFull);
     const uint32_t nchunk = (st + tile_bytes + 15) / 16;
-    for (uint32_t ch = threadIdx.x; ch < nchunk; ch += kWG) {
-      const uint32_t off = ch * 16;
-      uint4 u = make_uint4(0, 0, 0, 0);
-      if (off + 16 <= avail) {
-        u = *reinterpret_cast<const uint4*>(base + off);
-      } else {
+    // every chunk of this thread's loads first, then the one chunk that
+    // holds the stream's end byte by byte (no read past in_bytes), then the
+    // stores to LDS: loads return in order, so a store waiting on its chunk
+    // between loads would hold back the next chunk's load
+    constexpr uint32_t NCH = ((15u + (uint32_t)(G::TILE * G::SUB * BYTES) + 15u) / 16u + kWG - 1u) / kWG;
+    uint4 u[NCH];
+#pragma unroll
+    for (uint32_t j = 0; j < NCH; ++j) {
+      const uint32_t ch = threadIdx.x + j * kWG;
+      u[j] = make_uint4(0, 0, 0, 0);
+      if (ch < nchunk && ch * 16 + 16 <= avail) u[j] = *reinterpret_cast<const uint4*>(base + ch * 16);
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < NCH; ++j) {
+      const uint32_t ch = threadIdx.x + j * kWG;
+      if (ch < nchunk && ch * 16 + 16 > avail) {
+        const uint32_t off = ch * 16;
         uint32_t wv[4] = {0, 0, 0, 0};
         for (uint32_t bq = 0; bq < 16; ++bq)
           if (off + bq < avail) wv[bq >> 2] |= (uint32_t)base[off + bq] << ((bq & 3) * 8);
-        u = make_uint4(wv[0], wv[1], wv[2], wv[3]);
+        u[j] = make_uint4(wv[0], wv[1], wv[2], wv[3]);
       }
-      reinterpret_cast<uint4*>(s_stage)[ch] = u;
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < NCH; ++j) {
+      const uint32_t ch = threadIdx.x + j * kWG;
+      if (ch < nchunk) reinterpret_cast<uint4*>(s_stage)[ch] = u[j];
     }
   }
 
@@ -511,13 +526,34 @@ __device__ __forceinline__ void decode_tile(const FieldD& a, uint32_t t, uint32_
   const uint32_t nnc_t = (uint32_t)std::min<uint64_t>(h.n_nc > r0 ? h.n_nc - r0 : 0, (uint64_t)TBLK);
   const uint8_t* kbytes_t = in + h.sec.kbytes + r0;
   const uint8_t* codes_t = in + h.sec.codes + r0 * (B / 4);
+  // every row's K byte and codes first (loads return in order: a row's
+  // loads issued after the previous row's use would wait on them)
+  uint32_t kraw[SUB], craw[SUB];
+#pragma unroll
+  for (int s = 0; s < SUB; ++s) {
+    const uint32_t rl = rk[s] - ((lig != 0 && nc[s]) ? 1u : 0u);
+    const bool have = nc[s] && rl < nnc_t;
+    kraw[s] = have ? (uint32_t)kbytes_t[rl] : 0u;
+    craw[s] = 0;
+    if (have) {  // loaded beside K, used only for a coded block
+      const uint8_t* cp = codes_t + rl * (B / 4) + (uint32_t)lig * (EPL / 4);
+      if constexpr (EPL == 8) {
+        craw[s] = *reinterpret_cast<const uint16_t*>(cp);  // byte order fixed below
+      } else {
+        uint32_t c = 0;
+#pragma unroll
+        for (int j = 0; j < EPL / 4; ++j) c = (c << 8) | cp[j];
+        craw[s] = c;
+      }
+    }
+  }
 #pragma unroll
   for (int s = 0; s < SUB; ++s) {
     // the group's first lane counted its block; the others see it counted
     const uint32_t rl = rk[s] - ((lig != 0 && nc[s]) ? 1u : 0u);
     const bool have = nc[s] && rl < nnc_t;
     bad = bad || (nc[s] && rl >= nnc_t);
-    int K = have ? (int)kbytes_t[rl] : 0;
+    int K = (int)kraw[s];
     if (K == kRawK) {
       K = -1;
     } else if (have && (K < Traits<T>::KMIN || K > Traits<T>::W)) {
@@ -525,17 +561,8 @@ __device__ __forceinline__ void decode_tile(const FieldD& a, uint32_t t, uint32_
       K = 0;
     }
     const int nb = K > 0 ? bytes_of(K) : 0;
-    uint32_t c = 0;
-    if (have) {  // loaded beside K, used only for a coded block
-      const uint8_t* cp = codes_t + rl * (B / 4) + (uint32_t)lig * (EPL / 4);
-      if constexpr (EPL == 8) {
-        const uint32_t v16 = *reinterpret_cast<const uint16_t*>(cp);
-        c = ((v16 & 0xFFu) << 8) | (v16 >> 8);
-      } else {
-#pragma unroll
-        for (int j = 0; j < EPL / 4; ++j) c = (c << 8) | cp[j];
-      }
-    }
+    uint32_t c = craw[s];
+    if constexpr (EPL == 8) c = ((c & 0xFFu) << 8) | (c >> 8);
     // stored bytes of the lane: nb per live value less its code. Codes of
     // values past the end are cleared; a code above nb marks the stream bad
     // and its row is then read as if all codes were 0, which keeps every
