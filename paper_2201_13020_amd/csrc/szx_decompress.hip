@@ -258,11 +258,41 @@ __device__ __forceinline__ StreamInfo read_header(const FieldD& a) {
   return h;
 }
 
-// Mid bytes of one non-constant block of nk values with K byte Kb and its
-// codes at cp; raises bad for a K outside [1 + E, W] or a code above the kept
-// bytes.
+// A block's code bytes as words of 16 codes (b = 8: one half word in the
+// low 16 bits), read through a buffer resource at byte offset off (reads past
+// its range return zeros). A block's codes start 16-byte aligned (the codes
+// section is, and each block holds b / 4 bytes), so from b = 64 on they load
+// as 16-byte words.
+template <int B>
+struct BlockCodes {
+  static constexpr uint32_t NW = B >= 16 ? B / 16 : 1;
+  uint32_t raw[NW];
+};
+template <int B>
+__device__ __forceinline__ void load_codes(__amdgpu_buffer_rsrc_t rs, uint32_t off, BlockCodes<B>& c) {
+  using v4u = unsigned int __attribute__((ext_vector_type(4)));
+  if constexpr (B >= 64) {
+#pragma unroll
+    for (uint32_t q = 0; q < BlockCodes<B>::NW / 4; ++q) {
+      const v4u u = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(off + 16u * q), 0, 0);
+      c.raw[4 * q + 0] = u.x;
+      c.raw[4 * q + 1] = u.y;
+      c.raw[4 * q + 2] = u.z;
+      c.raw[4 * q + 3] = u.w;
+    }
+  } else if constexpr (B >= 16) {
+#pragma unroll
+    for (uint32_t j = 0; j < BlockCodes<B>::NW; ++j)
+      c.raw[j] = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)(off + 4u * j), 0, 0);
+  } else {
+    c.raw[0] = __builtin_amdgcn_raw_buffer_load_b16(rs, (int)off, 0, 0);
+  }
+}
+
+// Mid bytes of one non-constant block of nk values with K byte Kb and codes
+// c; raises bad for a K outside [1 + E, W] or a code above the kept bytes.
 template <typename T, int B>
-__device__ __forceinline__ uint32_t block_mid_bytes(const uint8_t* cp, uint32_t Kb, uint32_t nk, bool& bad) {
+__device__ __forceinline__ uint32_t block_mid_bytes(const BlockCodes<B>& c, uint32_t Kb, uint32_t nk, bool& bad) {
   constexpr int BYTES = Traits<T>::BYTES;
   if (Kb == kRawK) return nk * BYTES;
   if ((int)Kb < Traits<T>::KMIN || (int)Kb > Traits<T>::W) {
@@ -271,32 +301,14 @@ __device__ __forceinline__ uint32_t block_mid_bytes(const uint8_t* cp, uint32_t 
   }
   const uint32_t nb = (uint32_t)bytes_of((int)Kb);
   uint32_t sum = 0, over = 0;
-  // B/4 code bytes, 4 codes per byte, first value in the top bits; read in
-  // aligned words of 16 codes (b = 8 has one half word)
-  constexpr uint32_t NW = B >= 16 ? B / 16 : 1;
-  // a block's codes start 16-byte aligned (the codes section is, and each
-  // block holds b / 4 bytes), so from b = 64 on they load as 16-byte words
-  uint32_t raw[NW];
-  if constexpr (B >= 64) {
+  // b/4 code bytes, 4 codes per byte, first value in the top bits
 #pragma unroll
-    for (uint32_t q = 0; q < NW / 4; ++q) {
-      const uint4 u = reinterpret_cast<const uint4*>(cp)[q];
-      raw[4 * q + 0] = u.x;
-      raw[4 * q + 1] = u.y;
-      raw[4 * q + 2] = u.z;
-      raw[4 * q + 3] = u.w;
-    }
-  } else if constexpr (B >= 16) {
-#pragma unroll
-    for (uint32_t j = 0; j < NW; ++j) raw[j] = reinterpret_cast<const uint32_t*>(cp)[j];
-  }
-#pragma unroll
-  for (uint32_t j = 0; j < NW; ++j) {
+  for (uint32_t j = 0; j < BlockCodes<B>::NW; ++j) {
     uint32_t w;
     if constexpr (B >= 16) {
-      w = __builtin_bswap32(raw[j]);
+      w = __builtin_bswap32(c.raw[j]);
     } else {
-      const uint32_t h2 = *reinterpret_cast<const uint16_t*>(cp);
+      const uint32_t h2 = c.raw[0] & 0xFFFFu;
       w = ((h2 & 0xFFu) << 24) | ((h2 >> 8) << 16);
     }
     const uint32_t first = 16 * j;  // value index of the top code of w
@@ -334,11 +346,14 @@ __device__ __forceinline__ void dindex_tile(const DBatch& b, const FieldD& a, ui
   const uint8_t* in = a.in;
   const uint64_t k0 = (uint64_t)t * CLS + (uint64_t)threadIdx.x * BPT;
   bool bad = false;
+  // a thread's blocks share one state byte (BPT divides 8): one load
+  static_assert(8 % BPT == 0, "a thread's state bits lie in one byte");
+  const uint32_t sbyte = k0 < a.nblk ? (uint32_t)in[h.sec.state + (k0 >> 3)] : 0u;
   uint32_t ncb = 0, cnt = 0;
 #pragma unroll
   for (int i = 0; i < BPT; ++i) {
     const uint64_t k = k0 + i;
-    const bool nc = k < a.nblk && ((in[h.sec.state + (k >> 3)] >> (k & 7)) & 1u);
+    const bool nc = k < a.nblk && ((sbyte >> ((uint32_t)(k0 & 7) + i)) & 1u);
     ncb |= (nc ? 1u : 0u) << i;
     cnt += nc ? 1u : 0u;
   }
@@ -352,13 +367,14 @@ __device__ __forceinline__ void dindex_tile(const DBatch& b, const FieldD& a, ui
   if (direct) {
     constexpr uint32_t W16 = kDirectRankTiles * (CLS / 8) / 16 / kWG;  // words per thread, at most
     const uint32_t n16 = t * (CLS / 8) / 16;
-    const uint4* sp = reinterpret_cast<const uint4*>(in + h.sec.state);
-    uint4 u[W16];
+    // a buffer resource over exactly those bytes: words past it read zero,
+    // so every lane issues the same loads (no branch, no waits between them)
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(in + h.sec.state), (short)0, (int)(n16 * 16u), 0x00020000);
+    using v4u = unsigned int __attribute__((ext_vector_type(4)));
+    v4u u[W16];
 #pragma unroll
-    for (uint32_t j = 0; j < W16; ++j) {
-      const uint32_t i = threadIdx.x + j * kWG;
-      u[j] = i < n16 ? sp[i] : make_uint4(0, 0, 0, 0);
-    }
+    for (uint32_t j = 0; j < W16; ++j) u[j] = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)((threadIdx.x + j * kWG) * 16u), 0, 0);
 #pragma unroll
     for (uint32_t j = 0; j < W16; ++j) pop += __popc(u[j].x) + __popc(u[j].y) + __popc(u[j].z) + __popc(u[j].w);
   }
@@ -377,19 +393,41 @@ __device__ __forceinline__ void dindex_tile(const DBatch& b, const FieldD& a, ui
   }
   __syncthreads();
   const uint64_t R0 = s_r0;
+  // The K bytes and codes of the tile's ranks [R0, R0 + tnc) that the
+  // stream holds, through buffer resources over just those bytes (32-bit
+  // offsets from the tile's first rank; reads past them return zeros): every
+  // load of the thread goes out before any of them is used.
+  const uint64_t have_nc = h.n_nc > R0 ? std::min<uint64_t>(h.n_nc - R0, (uint64_t)tnc) : 0;
+  const __amdgpu_buffer_rsrc_t rk_ = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<uint8_t*>(in + h.sec.kbytes + R0), (short)0, (int)have_nc, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rc_ = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<uint8_t*>(in + h.sec.codes + R0 * (B / 4)), (short)0, (int)(have_nc * (B / 4)), 0x00020000);
+  uint32_t kbv[BPT];
+  BlockCodes<B> cv[BPT];
+#pragma unroll
+  for (int i = 0; i < BPT; ++i) {
+    // this block's rank from the tile's first: rex plus the thread's
+    // non-constant blocks before it (constant blocks read far past the range)
+    const uint32_t rl = rex + (uint32_t)__popc(ncb & ((1u << i) - 1u));
+    const bool live = (ncb >> i) & 1u;
+    kbv[i] = __builtin_amdgcn_raw_buffer_load_b8(rk_, live ? (int)rl : 0x40000000, 0, 0);
+    // up to b = 128 (32 code bytes a block); larger blocks load theirs as
+    // they are counted, which keeps their registers in bounds
+    if constexpr (B <= 128) load_codes<B>(rc_, live ? rl * (uint32_t)(B / 4) : 0x40000000u, cv[i]);
+  }
   uint32_t mid = 0;
-  uint64_t r = R0 + rex;
 #pragma unroll
   for (int i = 0; i < BPT; ++i) {
     const uint64_t k = k0 + i;
     if ((ncb >> i) & 1u) {
-      if (r < h.n_nc) {
+      const uint32_t rl = rex + (uint32_t)__popc(ncb & ((1u << i) - 1u));
+      if ((uint64_t)rl < have_nc) {
         const uint32_t nk = (uint32_t)std::min<uint64_t>((uint64_t)B, a.n - k * B);
-        mid += block_mid_bytes<T, B>(in + h.sec.codes + r * (B / 4), in[h.sec.kbytes + r], nk, bad);
+        if constexpr (B > 128) load_codes<B>(rc_, rl * (uint32_t)(B / 4), cv[i]);
+        mid += block_mid_bytes<T, B>(cv[i], kbv[i], nk, bad);
       } else {
         bad = true;
       }
-      ++r;
     }
   }
   uint32_t tmid;
