@@ -487,25 +487,30 @@ __device__ __forceinline__ void classify_tile(const FieldC& f, uint32_t t, uint3
   const uint64_t k0 = (uint64_t)t * CLS + (uint64_t)threadIdx.x * BPT;
   static_assert(BPT == 4, "four blocks per thread");
   // a thread's blocks are consecutive and start 16-byte aligned in the
-  // extrema, mu and plan arrays, so a full group moves as 16-byte words
+  // extrema, mu and plan arrays, so a full group moves as 16-byte words. The
+  // extrema come through a buffer resource over the tile's blocks (reads
+  // past the field's last block return zeros): one load form for every lane,
+  // so the range slots' loads below go out before any of them is waited for
   const bool full = k0 + BPT <= nblk;
   U kmin[BPT], kmax[BPT];
-  if (full) {
+  {
+    const uint64_t kt = (uint64_t)t * CLS;
+    const uint32_t nb_t = (uint32_t)std::min<uint64_t>(nblk - kt, (uint64_t)CLS);
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<U*>(stats + 2 * kt), (short)0, (int)(nb_t * 2u * (uint32_t)sizeof(U)), 0x00020000);
+    using v4u = unsigned int __attribute__((ext_vector_type(4)));
     U w[2 * BPT];
     constexpr int NQ = 2 * BPT * (int)sizeof(U) / 16;
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) reinterpret_cast<uint4*>(w)[q] = reinterpret_cast<const uint4*>(stats + 2 * k0)[q];
+    for (int q = 0; q < NQ; ++q) {
+      const v4u u = __builtin_amdgcn_raw_buffer_load_b128(
+          rs, (int)((uint32_t)threadIdx.x * (uint32_t)(2 * BPT * sizeof(U)) + 16u * (uint32_t)q), 0, 0);
+      reinterpret_cast<v4u*>(w)[q] = u;
+    }
 #pragma unroll
     for (int i = 0; i < BPT; ++i) {
       kmin[i] = w[2 * i];
       kmax[i] = w[2 * i + 1];
-    }
-  } else {
-#pragma unroll
-    for (int i = 0; i < BPT; ++i) {
-      const uint64_t k = k0 + i;
-      kmin[i] = k < nblk ? stats[2 * k] : (U)0;
-      kmax[i] = k < nblk ? stats[2 * k + 1] : (U)0;
     }
   }
   const bool clean = *f.clean == kCleanWord;
