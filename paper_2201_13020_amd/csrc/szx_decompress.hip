@@ -544,12 +544,24 @@ __device__ __forceinline__ void decode_tile(const FieldD& a, uint32_t t, uint32_
   int cnt[SUB];
   uint32_t first_of[SUB];
   T mu[SUB];
+  // every row's state byte and mu load before any is used (loads return in
+  // order: a row's loads issued after the previous row's use would wait)
+  uint32_t sbyte[SUB];
+#pragma unroll
+  for (int s = 0; s < SUB; ++s) {
+    const uint32_t lk = (uint32_t)(s * TB + g);
+    sbyte[s] = 0;
+    mu[s] = (T)0;
+    if (lk < nblk_t) {
+      sbyte[s] = state_t[lk >> 3];
+      mu[s] = mus_t[lk];
+    }
+  }
 #pragma unroll
   for (int s = 0; s < SUB; ++s) {
     const uint32_t lk = (uint32_t)(s * TB + g);
     const bool inb = lk < nblk_t;
-    nc[s] = inb && ((state_t[lk >> 3] >> (lk & 7)) & 1u);
-    mu[s] = inb ? mus_t[lk] : (T)0;
+    nc[s] = inb && ((sbyte[s] >> (lk & 7)) & 1u);
     // values from this lane's first one to the tile's end
     const int rem = (int)nval_t - (int)(lk * B) - lig * EPL;
     cnt[s] = inb ? (rem < 0 ? 0 : (rem > EPL ? EPL : rem)) : 0;
