@@ -1008,7 +1008,17 @@ __device__ __forceinline__ void encode_pass(const CBatch& b, uint32_t* s_scan, u
     if constexpr (BATCH == kSingle) {
       if (threadIdx.x == 0) *s_base = scan_wait(fp.enc_mid, p_tile, p_bytes, &fp.ctr->err, 1u, first_poll);
     } else if (threadIdx.x < kWave) {
-      const uint64_t p = lookback_resolve<1>(fp.enc_mid, p_tile, p_bytes, &fp.ctr->err, 1u);
+      // the predecessor's word was read before the next tile's loads: when
+      // it already holds its inclusive prefix (the common case by now), that
+      // is this tile's offset, published as the look-back would
+      const uint64_t w0 = __shfl(first_poll, 0);
+      uint64_t p;
+      if (p_tile > 0 && (w0 >> 62) == 2) {
+        p = w0 & kValueMask;
+        if (threadIdx.x == 0) status_store(fp.enc_mid + p_tile, kFlagIncl | ((p + p_bytes) & kValueMask));
+      } else {
+        p = lookback_resolve<1>(fp.enc_mid, p_tile, p_bytes, &fp.ctr->err, 1u);
+      }
       if (threadIdx.x == 0) *s_base = p;
     }
     __syncthreads();
@@ -1187,6 +1197,9 @@ __device__ __forceinline__ void encode_pass(const CBatch& b, uint32_t* s_scan, u
     uint64_t first_poll = 0;
     if constexpr (BATCH == kSingle) {
       if (pend && threadIdx.x == 0) first_poll = status_load(field_at<BATCH>(b, p_field).enc_mid + p_tile);
+    } else {  // a batch: the predecessor's word, for the look-back's shortcut
+      if (pend && threadIdx.x == 0 && p_tile > 0)
+        first_poll = status_load(field_at<BATCH>(b, p_field).enc_mid + p_tile - 1);
     }
     if (more) load(cur, gt);
     if (pend) flush(first_poll);
