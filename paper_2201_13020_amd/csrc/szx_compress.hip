@@ -1095,7 +1095,7 @@ __device__ __forceinline__ void encode_pass(const CBatch& b, uint32_t* s_scan, u
           K = group_all<LPB>(ok1) ? K1 : -1;
         }
         raw = K < 0;
-        if (raw) {  // byte-swapped here, so that every string below is byte_swap(q) >> 8 ci
+        if (raw) {  // byte-swapped here, so that every string below is byte_swap(q) less its ci low bytes
 #pragma unroll
           for (int i = 0; i < EPL; ++i) q[i] = byte_swap(bits_of(cur.x[s][i]));
         }
